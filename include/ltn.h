@@ -1,0 +1,301 @@
+/*
+ * ltn.h -- C ABI of the sliced tensor-network contraction library (libltn).
+ *
+ * The library evaluates amplitudes of a random quantum circuit by
+ * contracting its tensor network along a contraction tree with a set of
+ * sliced edges, after Chen et al., "Lifetime-based Optimization for
+ * Simulating Quantum Circuits on a New Sunway Supercomputer" (PPoPP'23):
+ *
+ *   network G = (V, E), w(e) = 2              (Sec. 2.1.1, Notation)
+ *   contraction path / rooted binary tree B   (Sec. 2.1.1)
+ *   slicing set S, 2^|S| independent subtasks whose results are summed
+ *                                             (Sec. 2.1.1, Eq. (2))
+ *   slice finder on the stem                  (Sec. 4.2, Algorithm 1)
+ *
+ * Conventions shared by every call:
+ *   - complex numbers are interleaved (re, im); complex64 = 2 x float,
+ *     complex128 = 2 x double;
+ *   - a tensor of rank r is a dense array of 2^r elements, row-major over
+ *     its index list (the first index is the slowest);
+ *   - an "index id" is an edge of the network, 0 <= id < n_indices;
+ *   - SSA path: leaves are 0..L-1, the k-th contraction creates id L+k;
+ *     path[2k], path[2k+1] are its two operands;
+ *   - slice id s: bit j (LSB = 0) of s is the value of the sliced index
+ *     S[j];
+ *   - output vector: one entry per assignment of the open indices, the
+ *     first open index is the most significant bit; sliced open indices
+ *     take their bits from the slice id (placement), the others are summed
+ *     over slices.
+ *
+ * Errors: every call returns an ltn_status; 0 is success, negative values
+ * are errors and ltn_last_error() returns a message (thread-local, valid
+ * until the next failing call on the same thread). No exception crosses
+ * the ABI. Host arrays passed in are borrowed for the duration of the call
+ * and copied. Device buffers passed in are owned by the caller and must
+ * outlive the stream work that uses them.
+ */
+#ifndef LTN_H
+#define LTN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ltn_status;
+enum {
+  LTN_OK = 0,
+  LTN_E_INVALID = -1, /* malformed input (shape, id, path, slice id ...)   */
+  LTN_E_CAP = -2,     /* a tensor's rank after slicing exceeds max_rank    */
+  LTN_E_NOMEM = -3,   /* workspace too small for one slice                 */
+  LTN_E_HIP = -4,     /* a HIP runtime call failed (message has the code)  */
+  LTN_E_STATE = -5,   /* call not valid in the plan's state (e.g. unbound) */
+  LTN_E_UNSUPPORTED = -6
+};
+
+/* Precision of the contraction steps (all accumulate in FP32 and sum the
+ * slices in FP64). */
+enum {
+  LTN_C64 = 0,        /* complex64 GEMMs on FP32 MFMA / FP32 VALU          */
+  LTN_SPLIT_F16 = 1,  /* each real part split into fp16 hi + lo (scaled)   */
+  LTN_SPLIT_BF16 = 2  /* each real part split into bf16 hi + lo            */
+};
+
+/* ------------------------------------------------------------------------
+ * Circuits and networks (host).
+ * ---------------------------------------------------------------------- */
+
+/* Gate kinds of the synthetic random circuits. Matrices are [out][in];
+ * two-qubit gates act on |q0 q1> with q0 the more significant qubit. */
+enum {
+  LTN_GATE_SQRT_X = 1, /* ((1+i)/2) I + ((1-i)/2) X                       */
+  LTN_GATE_SQRT_Y = 2, /* ((1+i)/2) I + ((1-i)/2) Y                       */
+  LTN_GATE_SQRT_W = 3, /* ((1+i)/2) I + ((1-i)/2) W, W = (X+Y)/sqrt 2     */
+  LTN_GATE_FSIM = 4,   /* fsim(theta = p[0], phi = p[1])                   */
+  LTN_GATE_U3 = 5,     /* Rz(p[0]) Ry(p[1]) Rz(p[2]), a parameterised leaf */
+  LTN_GATE_MATRIX = 6  /* explicit 2x2 or 4x4 complex128 matrix in m[]     */
+};
+
+typedef struct ltn_gate {
+  int32_t kind;
+  int32_t q0, q1;   /* q1 = -1 for single-qubit gates                      */
+  int32_t param_id; /* u3 gates: 0.. in circuit order; -1 otherwise        */
+  double p[3];
+  double m[32];     /* LTN_GATE_MATRIX: row-major complex128 (re, im)      */
+} ltn_gate;
+
+/* A tensor network, as consumed by the planner and by ltn_plan_load.
+ * Every index must lie in exactly two leaves (closed) or exactly one leaf
+ * (open; then it must be listed in open_ids). */
+typedef struct ltn_network {
+  int32_t n_leaves;
+  const int64_t* leaf_off;  /* [n_leaves+1] CSR offsets into index_ids    */
+  const int32_t* index_ids; /* per leaf, axis order (first = slowest)     */
+  const float* leaf_data;   /* complex64 data of each leaf, concatenated
+                               in leaf order, 2^rank elements each; the
+                               data of parameterised leaves is ignored    */
+  int32_t n_open;
+  const int32_t* open_ids;  /* output order, first = most significant     */
+  int32_t n_indices;
+  const int32_t* param_leaf; /* [n_leaves] u3 gate id or -1; may be NULL  */
+} ltn_network;
+
+typedef struct ltn_netbuf ltn_netbuf; /* an owned network built by the library */
+
+/* Build the network <b| C |0> of a circuit (gates in order) and absorb its
+ * non-parameterised rank-1 and rank-2 tensors (Sec. 2.1.2: preprocessing
+ * "rank-1 and rank-2 tensors are absorbed"). closed_bits[q] is the fixed
+ * output bit of qubit q, or -1 for an open qubit (open indices are listed
+ * in ascending qubit order). Index ids are given in creation order (the
+ * initial wire of qubit q is id q, then every gate creates one id per
+ * qubit it acts on); tensors are |0> per qubit, the gates, then <b_q| per
+ * closed qubit. Absorption repeatedly merges the lowest-id tensor of rank
+ * <= 2 that is not a u3 leaf into its lowest-id non-u3 neighbour (axes:
+ * the neighbour's unshared axes, then the absorbed tensor's), in
+ * complex128, then rounds to complex64; ids are then renumbered densely.
+ * absorb = 0 skips absorption. */
+ltn_status ltn_network_build(int32_t n_qubits, const ltn_gate* gates, int32_t n_gates,
+                             const int32_t* closed_bits, int32_t absorb, ltn_netbuf** out);
+/* Fill *view with pointers into the netbuf (valid until ltn_netbuf_free). */
+ltn_status ltn_netbuf_view(const ltn_netbuf* nb, ltn_network* view);
+/* complex128 leaf data (before rounding), concatenated like leaf_data. */
+ltn_status ltn_netbuf_data128(const ltn_netbuf* nb, const double** data);
+void ltn_netbuf_free(ltn_netbuf* nb);
+
+/* ------------------------------------------------------------------------
+ * Host planner: path, tree costs, lifetimes, slice finder.
+ * ---------------------------------------------------------------------- */
+
+/* Greedy contraction path. Among pairs of live tensors that share an index
+ * (ignoring the indices in `exclude`), contract the pair with the smallest
+ * key; when no pair shares an index, join the two lowest ids.
+ *   key = (2^rc - alpha (2^ra + 2^rb)) * (1 + tau u)  if the bracket > 0
+ *         (2^rc - alpha (2^ra + 2^rb)) * (1 - tau u)  otherwise
+ * evaluated in IEEE double in that order (rc, ra, rb = ranks of the result
+ * and operands), with u in [0,1) from SplitMix64 keyed by (seed, step, a,
+ * b); ties go to the smallest (lower id, higher id). tau = 0, alpha = 1 is
+ * the plain greedy rule. path_out: [2*(L-1)]. */
+ltn_status ltn_greedy_path(const ltn_network* net, const int32_t* exclude, int32_t n_exclude,
+                           double alpha, double tau, uint64_t seed, int32_t* path_out);
+
+/* Costs of a tree with slicing set S (exact integers as little-endian
+ * 64-bit words, and their log2):
+ *   cost      = Eq. (1) C(B), summed over the contraction nodes;
+ *   sliced    = Eq. (4) C(B,S);
+ *   space     = log2 of the largest tensor after slicing;
+ *   overhead  = Eq. (2) C(B,S) / C(B). */
+typedef struct ltn_costs {
+  double log2_cost, log2_sliced, overhead;
+  int32_t space_log2, space_log2_unsliced;
+  uint64_t cost_words[4];
+  uint64_t sliced_words[4];
+  int32_t stem_len;
+} ltn_costs;
+ltn_status ltn_tree_costs(const ltn_network* net, const int32_t* path, const int32_t* S,
+                          int32_t n_sliced, ltn_costs* out);
+
+/* Stem of the tree (Sec. 4.2): the root-to-leaf path of largest summed
+ * Eq. (1) node cost, as node ids ordered leaf -> root (ties: larger
+ * subtree cost, then smaller id). stem_out capacity = cap. */
+ltn_status ltn_tree_stem(const ltn_network* net, const int32_t* path, int32_t* stem_out,
+                         int32_t cap, int32_t* len);
+
+/* Slice finder (Algorithm 1) on the stem under target rank t, starting
+ * from the indices in `pre` (already sliced), followed by a fix-up that
+ * slices, for every tree tensor still above t (SSA order), its unsliced
+ * index held by the most tree tensors (then the smaller id). Algorithm 1
+ * tie-breaks: sT = M[0] if M[0].dim < M[N-1].dim else M[N-1]; "longest
+ * lifetime" = most tensors of the current M holding the index, then most
+ * tree tensors, then the smaller id. t < 0 means no cap (S = pre).
+ * S_out receives pre followed by the added indices (capacity cap). */
+ltn_status ltn_slice_finder(const ltn_network* net, const int32_t* path, int32_t t,
+                            const int32_t* pre, int32_t n_pre, int32_t* S_out, int32_t cap,
+                            int32_t* n_sliced);
+
+/* Randomised greedy search: for every (alpha, tau, seed) trial below, run
+ * ltn_greedy_path then ltn_slice_finder, and keep the trial with the
+ * smallest (C(B,S), |S|, trial number). Trials are numbered alpha-major,
+ * then tau, then seed (0..n_seeds-1); trials with tau = 0 use seed 0 only. */
+typedef struct ltn_search_opts {
+  int32_t n_alpha;
+  const double* alphas;
+  int32_t n_tau;
+  const double* taus;
+  int32_t n_seeds;
+  uint64_t seed_base;
+} ltn_search_opts;
+ltn_status ltn_path_search(const ltn_network* net, int32_t t, const int32_t* pre, int32_t n_pre,
+                           const ltn_search_opts* opts, int32_t* path_out, int32_t* S_out,
+                           int32_t cap, int32_t* n_sliced, int32_t* best_trial);
+
+/* ------------------------------------------------------------------------
+ * Plans and execution.
+ * ---------------------------------------------------------------------- */
+
+typedef struct ltn_plan ltn_plan;
+
+typedef struct ltn_options {
+  int32_t max_rank;      /* cap check t: every tensor after slicing must
+                            have rank <= max_rank (negative: no check)     */
+  int32_t batch;         /* slices per batch; 0 = as many as fit          */
+  int32_t fat_threshold; /* steps with min(k, n, m) bits >= this go to the
+                            MFMA GEMM (0 = library default)                */
+  int32_t reserved;
+} ltn_options;
+
+/* Compile a plan (host only, no device call): validate the network, the
+ * SSA path and the slicing set, assign every tensor its layout (unsliced
+ * indices sorted by the step that contracts them, earliest = lowest bit;
+ * open indices last, in output order), give every step its (m, k, n) bit
+ * groups and kernel, and lay tensors out in a per-slice arena by liveness.
+ * Errors: LTN_E_INVALID (index in more than two leaves, open index not
+ * listed, path not an SSA cover, duplicate / unknown sliced id, rank > 62),
+ * LTN_E_CAP (max_rank exceeded). */
+ltn_status ltn_plan_load(const ltn_network* net, const int32_t* path_ssa, int32_t n_sliced,
+                         const int32_t* sliced_ids, const ltn_options* opt, ltn_plan** out);
+
+typedef struct ltn_plan_info {
+  int32_t n_leaves, n_steps, n_sliced, n_open, n_open_unsliced, n_params;
+  int32_t batch;                /* 0 until bound                          */
+  int32_t root_rank;
+  double macs_per_slice;        /* sum over steps of 2^(m+k+n)            */
+  uint64_t macs_words[2];       /* the same, exact                        */
+  uint64_t arena_bytes_per_slice;
+  uint64_t grad_arena_bytes_per_slice;
+  uint64_t const_bytes;         /* batch-independent part of a workspace  */
+  const int32_t* sliced_ids;    /* [n_sliced], bit order of slice ids     */
+} ltn_plan_info;
+ltn_status ltn_plan_describe(const ltn_plan* plan, ltn_plan_info* out);
+
+/* Kernel classes a step can use. */
+enum { LTN_K_SMALL = 0, LTN_K_MFMA = 1 };
+
+typedef struct ltn_step_info {
+  int32_t left, right, out; /* SSA ids                                      */
+  int32_t a_is_left;        /* operand A (rows m) is the left SSA operand   */
+  int32_t m, k, n;          /* bits of the free-A, contracted, free-B groups */
+  int32_t kernel;           /* LTN_K_*                                       */
+  const int32_t* a_idx;     /* A's unsliced indices, lowest bit first       */
+  const int32_t* b_idx;     /* B's unsliced indices, lowest bit first       */
+  const int32_t* c_idx;     /* the output's indices, lowest bit first       */
+  uint64_t c_mask_a;        /* output bits that come from A (rest from B)   */
+  uint64_t arena_off_a, arena_off_b, arena_off_c; /* per-slice byte offsets */
+} ltn_step_info;
+ltn_status ltn_plan_step(const ltn_plan* plan, int32_t step, ltn_step_info* out);
+
+/* Bytes of workspace for `batch` slices per batch (grad != 0: enough for
+ * ltn_execute_grad as well). */
+ltn_status ltn_workspace_size(const ltn_plan* plan, int32_t batch, int32_t grad, size_t* bytes);
+
+/* Bind device memory and a HIP stream (hipStream_t passed as void*; NULL =
+ * the default stream). The batch size becomes the largest that fits in
+ * `bytes` (capped by ltn_options.batch when set); the grad flag must match
+ * the one used for ltn_workspace_size. Uploads leaf data (async on the
+ * stream). Errors: LTN_E_NOMEM if not even one slice fits. */
+ltn_status ltn_bind(ltn_plan* plan, void* d_workspace, size_t bytes, int32_t grad, void* stream);
+
+/* Contract the listed slices (host array of n ids, each < 2^|S|) and
+ * ADD the result into d_out (complex128, 2^n_open entries, device).
+ * Slices are summed in FP64, in batches of the bound batch size; within a
+ * batch in ascending position, batches in call order. Asynchronous on the
+ * bound stream. Errors: LTN_E_STATE (unbound), LTN_E_INVALID (bad id /
+ * mode). */
+ltn_status ltn_execute(ltn_plan* plan, const uint64_t* slice_ids, uint64_t n, int32_t mode,
+                       void* d_out);
+/* Same for the slice ids begin .. end-1. */
+ltn_status ltn_execute_range(ltn_plan* plan, uint64_t begin, uint64_t end, int32_t mode,
+                             void* d_out);
+
+/* Rebuild every parameterised (u3) leaf from angles on the device:
+ * d_angles is float64 [n_params] laid out [gate][a, b, c] with
+ * U = Rz(a) Ry(b) Rz(c). Asynchronous on the bound stream. */
+ltn_status ltn_set_params(ltn_plan* plan, const double* d_angles);
+
+/* Gradient of a real loss with respect to the u3 angles, by an adjoint
+ * contraction that recomputes every slice's intermediates. d_cotangent is
+ * the loss gradient with respect to the output vector (complex128,
+ * 2^n_open entries, PyTorch convention dL/dRe + i dL/dIm). Adds the
+ * forward result into d_out (may be NULL) and dL/dangle into d_angle_grad
+ * (float64 [n_params]). Requires a plan bound with grad != 0. */
+ltn_status ltn_execute_grad(ltn_plan* plan, const uint64_t* slice_ids, uint64_t n, int32_t mode,
+                            const void* d_cotangent, void* d_out, double* d_angle_grad);
+
+/* Time every distinct step shape with the candidate kernel configurations
+ * on the bound stream and keep the fastest (cached in `cache_path` as JSON
+ * when non-NULL). Synchronises the stream. */
+ltn_status ltn_autotune(ltn_plan* plan, int32_t mode, const char* cache_path);
+
+/* Per-step timing of one batch (debug replay outside the graph): writes
+ * n_steps floats of milliseconds into ms_out. Synchronises the stream. */
+ltn_status ltn_profile_steps(ltn_plan* plan, uint64_t first_slice, int32_t mode, float* ms_out);
+
+void ltn_plan_free(ltn_plan* plan);
+const char* ltn_last_error(void);
+const char* ltn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LTN_H */

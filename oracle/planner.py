@@ -1,0 +1,266 @@
+"""Contraction path, contraction tree, cost formulas, lifetimes, Algorithm 1.
+
+Written from the paper:
+
+* contraction tree B (Sec. 2.1.1): one node per contraction, its tensor's
+  indices are the symmetric difference of its children's (Lemma 1);
+* Eq. (1)  C(B)   = sum over contractions of 2^|s_v1 u s_v2 u s_v3|;
+  read here as the contraction (internal) nodes only; leaf reads and the
+  final scalar node carry no multiply-adds;
+* Eq. (2)  O(B,S) = C_slice(B) 2^|S| / C_original(B);
+* Eq. (4)  C(B,S) = sum_V 2^(|s_V| + |S| - |S n s_V|);
+* space cost = largest tensor, max 2^rank;
+* lifetime of an index (Sec. 3.1 Definition) = the tree tensors holding it;
+* stem (Sec. 4.2) = the most computationally intensive root-to-leaf path;
+* Algorithm 1 (slice finder) on the stem, then a fix-up for off-stem tensors.
+
+The greedy path is not in the paper (which takes its paths from cotengra);
+it follows the usual greedy rule: among tensor pairs sharing an index,
+contract the pair minimising size(out) - alpha (size(a) + size(b)),
+optionally scaled by (1 +- tau u) with a keyed uniform u (randomised
+greedy); ties go to the lexicographically smallest (lower id, higher id);
+when no pair shares an index, the two lowest ids are joined by an outer
+product. SSA ids: leaves 0..L-1, the k-th contraction creates L+k.
+
+Tie-breaks of Algorithm 1 (the paper does not give them):
+* ``sT`` = M[0] if M[0].dim < M[-1].dim else M[-1] (ties go to M[-1]);
+* ``T.dim`` = rank after removing the indices already in S;
+* "longest lifetime" = most tensors of the current M holding the index,
+  then most tensors of the whole tree, then the smaller index id;
+* off-stem tensors still above t afterwards (post-order, SSA order): add
+  their unsliced index with the longest whole-tree lifetime (then smaller
+  id) until they fit.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Optional, Sequence, Tuple
+
+
+MASK64 = (1 << 64) - 1
+
+
+def splitmix64(x: int) -> int:
+    """SplitMix64 (Steele, Lea, Flood 2014): one step from state x."""
+    x = (x + 0x9E3779B97F4A7C15) & MASK64
+    z = x
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def keyed_uniform(seed: int, step: int, a: int, b: int) -> float:
+    """Uniform double in [0, 1) that depends only on (seed, step, a, b)."""
+    h = splitmix64(seed & MASK64)
+    h = splitmix64(h ^ step)
+    h = splitmix64(h ^ a)
+    h = splitmix64(h ^ b)
+    return (h >> 11) * (2.0 ** -53)
+
+
+def pair_key(rc: int, ra: int, rb: int, alpha: float, tau: float, u: float) -> float:
+    """Greedy score of contracting two tensors of ranks ra, rb into rank rc,
+    in IEEE double, in this exact order of operations."""
+    t1 = math.ldexp(1.0, ra) + math.ldexp(1.0, rb)
+    t2 = alpha * t1
+    base = math.ldexp(1.0, rc) - t2
+    if tau > 0.0:
+        f = tau * u
+        if base > 0.0:
+            base = base * (1.0 + f)
+        else:
+            base = base * (1.0 - f)
+    return base
+
+
+def greedy_path(leaf_indices: Sequence[Sequence[int]], alpha: float = 1.0, tau: float = 0.0,
+                seed: int = 0, exclude: Sequence[int] = ()) -> List[Tuple[int, int]]:
+    """Greedy SSA path; alpha = 1, tau = 0 is the plain rule, other values
+    give the randomised variant (key in ``pair_key``, noise from
+    ``keyed_uniform``). Indices in ``exclude`` are ignored."""
+    ex = set(exclude)
+    L = len(leaf_indices)
+    live: Dict[int, frozenset] = {i: frozenset(x for x in ix if x not in ex)
+                                  for i, ix in enumerate(leaf_indices)}
+    owner: Dict[int, set] = {}
+    for t, ix in live.items():
+        for x in ix:
+            owner.setdefault(x, set()).add(t)
+    path = []
+    nxt = L
+    step = 0
+    while len(live) > 1:
+        best = None
+        for x, ts in owner.items():
+            if len(ts) != 2:
+                continue
+            a, b = sorted(ts)
+            ia, ib = live[a], live[b]
+            u = keyed_uniform(seed, step, a, b) if tau > 0.0 else 0.0
+            key = (pair_key(len(ia ^ ib), len(ia), len(ib), alpha, tau, u), a, b)
+            if best is None or key < best:
+                best = key
+        if best is None:
+            a, b = sorted(live)[:2]
+        else:
+            _, a, b = best
+        new = live[a] ^ live[b]
+        for x in live[a] | live[b]:
+            owner[x].discard(a)
+            owner[x].discard(b)
+            if x in new:
+                owner[x].add(nxt)
+            elif not owner[x]:
+                del owner[x]
+        del live[a], live[b]
+        live[nxt] = new
+        path.append((a, b))
+        nxt += 1
+        step += 1
+    return path
+
+
+class Tree:
+    """Rooted binary contraction tree of an SSA path."""
+
+    def __init__(self, leaf_indices: Sequence[Sequence[int]], path: Sequence[Tuple[int, int]]):
+        self.L = len(leaf_indices)
+        self.path = [tuple(p) for p in path]
+        self.sets: List[frozenset] = [frozenset(ix) for ix in leaf_indices]
+        self.children: List[Optional[Tuple[int, int]]] = [None] * self.L
+        self.parent: List[int] = [-1] * (self.L + len(self.path))
+        for k, (a, b) in enumerate(self.path):
+            v = self.L + k
+            self.sets.append(self.sets[a] ^ self.sets[b])
+            self.children.append((a, b))
+            self.parent[a] = v
+            self.parent[b] = v
+        self.root = len(self.sets) - 1
+
+    def nodes(self) -> range:
+        return range(self.L, len(self.sets))
+
+    def node_set(self, v: int) -> frozenset:
+        """s_v1 u s_v2 u s_v3 of contraction node v."""
+        a, b = self.children[v]
+        return self.sets[a] | self.sets[b]
+
+    def cost(self) -> int:
+        """Eq. (1)."""
+        return sum(1 << len(self.node_set(v)) for v in self.nodes())
+
+    def sliced_cost(self, S: Sequence[int]) -> int:
+        """Eq. (4)."""
+        S = set(S)
+        tot = 0
+        for v in self.nodes():
+            sv = self.node_set(v)
+            tot += 1 << (len(sv) + len(S) - len(S & sv))
+        return tot
+
+    def overhead(self, S: Sequence[int]) -> float:
+        """Eq. (2)."""
+        return self.sliced_cost(S) / self.cost()
+
+    def space(self, S: Sequence[int] = ()) -> int:
+        S = set(S)
+        return max(1 << len(s - S) for s in self.sets)
+
+    def lifetime(self, index: int) -> List[int]:
+        """Tree tensors (node ids) holding ``index``."""
+        return [v for v, s in enumerate(self.sets) if index in s]
+
+    def stem(self) -> List[int]:
+        """Root-to-leaf path of largest summed node cost, as node ids
+        ordered leaf -> root. Ties: the child with the larger subtree cost,
+        then the smaller id."""
+        best: Dict[int, int] = {}
+        sub: Dict[int, int] = {}
+        for v in range(len(self.sets)):
+            if v < self.L:
+                best[v] = 0
+                sub[v] = 0
+            else:
+                a, b = self.children[v]
+                c = 1 << len(self.node_set(v))
+                best[v] = c + max(best[a], best[b])
+                sub[v] = c + sub[a] + sub[b]
+        out = [self.root]
+        v = self.root
+        while v >= self.L:
+            a, b = self.children[v]
+            v = min((a, b), key=lambda u: (-best[u], -sub[u], u))
+            out.append(v)
+        return out[::-1]
+
+
+def slice_finder(tree: Tree, t: int, pre: Sequence[int] = (),
+                 stem: Optional[List[int]] = None) -> List[int]:
+    """Algorithm 1 on the stem, then the off-stem fix-up, starting from the
+    already-sliced indices ``pre``. Returns S = pre + the indices in the
+    order they were added (bit j of a slice id is the value of S[j]).
+    t < 0 means no cap."""
+    S: List[int] = list(pre)
+    if t < 0:
+        return S
+    if pre:
+        # the pre-sliced indices are fixed before anything else: the tree,
+        # its stem and all lifetimes are taken without them
+        ps = set(pre)
+        tree = Tree([[x for x in tree.sets[v] if x not in ps] for v in range(tree.L)], tree.path)
+    inS = set()
+    M = list(tree.stem() if stem is None else stem)
+    whole = {}
+    for s in tree.sets:
+        for x in s:
+            whole[x] = whole.get(x, 0) + 1
+
+    def dim(v):
+        return len(tree.sets[v] - inS)
+
+    def lifetimes(M):
+        lf = {}
+        for v in M:
+            for x in tree.sets[v]:
+                lf[x] = lf.get(x, 0) + 1
+        return lf
+
+    M = [v for v in M]
+    lf = lifetimes(M)
+    while M:
+        sT = M[0] if dim(M[0]) < dim(M[-1]) else M[-1]
+        need = dim(sT) - t
+        if need > 0:
+            cand = sorted((x for x in tree.sets[sT] if x not in inS),
+                          key=lambda x: (-lf[x], -whole[x], x))
+            for x in cand[:need]:
+                S.append(x)
+                inS.add(x)
+        M = [v for v in M if dim(v) > t]
+        lf = lifetimes(M)
+    for v in range(len(tree.sets)):
+        while dim(v) > t:
+            x = min((y for y in tree.sets[v] if y not in inS), key=lambda y: (-whole[y], y))
+            S.append(x)
+            inS.add(x)
+    return S
+
+
+def path_search(leaf_indices, t: int, pre: Sequence[int] = (), alphas=(1.0,), taus=(0.0,),
+                n_seeds: int = 1, seed_base: int = 0):
+    """Randomised greedy trials (alpha-major, then tau, then seed; tau = 0
+    runs seed 0 only), each followed by the slice finder; keep the smallest
+    (C(B,S), |S|, trial number). Returns (path, S, trial)."""
+    best = None
+    trial = 0
+    for alpha in alphas:
+        for tau in taus:
+            for sd in range(n_seeds if tau > 0.0 else 1):
+                p = greedy_path(leaf_indices, alpha, tau, seed_base + sd, exclude=pre)
+                tr = Tree(leaf_indices, p)
+                S = slice_finder(tr, t, pre)
+                key = (tr.sliced_cost(S), len(S), trial)
+                if best is None or key < best[0]:
+                    best = (key, p, S, trial)
+                trial += 1
+    return best[1], best[2], best[3]
