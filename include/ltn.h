@@ -291,6 +291,12 @@ ltn_status ltn_autotune(ltn_plan* plan, int32_t mode, const char* cache_path);
  * n_steps floats of milliseconds into ms_out. Synchronises the stream. */
 ltn_status ltn_profile_steps(ltn_plan* plan, uint64_t first_slice, int32_t mode, float* ms_out);
 
+/* Kernel chosen for a step after ltn_bind / ltn_autotune: cfg = MFMA tile
+ * configuration (-1: generic kernel), swap = operands exchanged on the MFMA
+ * (rows from B), tk = generic kernel threads per output. */
+ltn_status ltn_step_kernel(const ltn_plan* plan, int32_t step, int32_t* cfg, int32_t* swap,
+                           int32_t* tk);
+
 void ltn_plan_free(ltn_plan* plan);
 const char* ltn_last_error(void);
 const char* ltn_version(void);

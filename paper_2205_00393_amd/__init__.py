@@ -1,0 +1,12 @@
+"""Sliced tensor-network contraction of random quantum circuits on MI355X.
+
+Host planner (network, greedy path, lifetime-based slicing) and HIP
+execution, both in libltn (C ABI in include/ltn.h); this package marshals
+arguments and lends PyTorch device memory and streams.
+"""
+from ._lib import LtnError, lib, MODES
+from .network import (Network, greedy_path, tree_costs, tree_stem, slice_finder, path_search)
+from .plan import Plan, Prepared, prepare
+
+__all__ = ["LtnError", "lib", "MODES", "Network", "greedy_path", "tree_costs", "tree_stem",
+           "slice_finder", "path_search", "Plan", "Prepared", "prepare"]

@@ -1,0 +1,85 @@
+// Device kernels of libltn and their host-side launchers (all asynchronous
+// on the given stream). Tensors are complex64 (float2); each batched
+// operand is a base pointer plus a per-slice stride in elements.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace ltn {
+
+constexpr int kMaxLeafRank = 32;
+
+// Gather of one leaf into its per-slice layout (Sec. 2.1.1: a sliced index
+// takes the value given by the slice id).
+struct GatherDesc {
+  int64_t src_off;   // element offset in the leaf-data area
+  int64_t dst_off;   // element offset of slice 0 in the arena
+  int32_t rank;      // unsliced rank (dst has 2^rank elements per slice)
+  int32_t nsl;       // number of sliced axes
+  int8_t src_bit[kMaxLeafRank];
+  int8_t sl_src_bit[kMaxLeafRank];
+  int8_t sl_bit[kMaxLeafRank];
+};
+
+struct ParamLeaf {
+  int64_t src_off;   // element offset of the 2x2 [out][in] data
+  int32_t gate;      // u3 gate number (angles 3*gate .. 3*gate+2)
+  int32_t gd;        // index of its GatherDesc (for cotangent scatter)
+};
+
+// Operand addressing of the generic contraction
+//   out[pdep(x, ox) | pdep(y, oy)] = sum_z P[pdep(x, px) | pdep(z, pz)]
+//                                        * Q[pdep(y, qy) | pdep(z, qz)]
+struct GenericDesc {
+  const float2* P;
+  const float2* Q;
+  float2* out;
+  int64_t sP, sQ, sO;    // per-slice strides (elements)
+  uint64_t px, pz, qy, qz, ox, oy;
+  int32_t xb, yb, zb;    // bit counts
+  int32_t conjQ;
+  int32_t accumulate;    // add into out instead of overwrite
+  int32_t nb;            // slices
+};
+
+void launch_set_ids(uint64_t* d_ids, const uint64_t* h_ids, int n, hipStream_t st);
+void launch_set_range(uint64_t* d_ids, uint64_t base, int n, hipStream_t st);
+void launch_gather(const GatherDesc* d_desc, int n_leaves, int max_elems, const float2* leafdata,
+                   float2* arena, const uint64_t* ids, int nb, hipStream_t st);
+void launch_reduce(const float2* root, int rank, uint64_t out_mask, const int32_t* sl_bits,
+                   const int32_t* out_bits, int n_sl, const uint64_t* ids, int nb, double* out,
+                   hipStream_t st);
+void launch_root_cotangent(const double* cot, int rank, uint64_t out_mask, const int32_t* sl_bits,
+                           const int32_t* out_bits, int n_sl, const uint64_t* ids, int nb,
+                           float2* rootcot, hipStream_t st);
+void launch_u3_build(const ParamLeaf* d_pl, int n, const double* angles, float2* leafdata,
+                     hipStream_t st);
+void launch_leaf_cot_accumulate(const ParamLeaf* d_pl, int n, const GatherDesc* gd,
+                                const float2* cot_arena, const uint64_t* ids, int nb,
+                                double* leafgrad, hipStream_t st);
+void launch_u3_adjoint(const ParamLeaf* d_pl, int n, const double* angles, const double* leafgrad,
+                       double* angle_grad, hipStream_t st);
+void launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+void launch_generic(const GenericDesc& d, int tk, hipStream_t st);
+
+// C[merge(m, n)] = sum_k A[m 2^k + k] B[n 2^k + k] on FP32 MFMA; the output
+// bit j comes from A's next free bit if (cmask >> j) & 1, else from B's.
+struct GemmDesc {
+  const float2* A;
+  const float2* B;
+  float2* C;
+  int64_t sA, sB, sC;
+  int32_t m, k, n;
+  uint64_t cmask;
+  int32_t nb;
+  int32_t cfg;           // tile configuration id
+  const uint32_t* scale_a; // split mode: per-slice max |x| bits of A
+  const uint32_t* scale_b;
+};
+int gemm_config_count();
+bool gemm_config_fits(int cfg, int m, int k, int n);
+const char* gemm_config_name(int cfg);
+void launch_cgemm(const GemmDesc& d, int mode, hipStream_t st);
+
+}  // namespace ltn

@@ -1,0 +1,79 @@
+// Compiled plan: what ltn_plan_load derives from (network, path, S).
+//
+// Layout rule: every tensor stores its unsliced indices ordered by the step
+// that contracts them, earliest lowest (bit 0 = fastest); ties by index id;
+// open indices come last, the last open index lowest, so the root tensor is
+// already in output order. With this rule the indices contracted at a step
+// are the lowest bits of both operands, so every step is
+//     C[merge(m, n)] = sum_k A[m * 2^k + k] * B[n * 2^k + k]
+// with no input transposition; the output order is a merge of A's and B's
+// free bits (each keeping its order), described by one bit mask.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+struct LeafPlan {
+  int32_t leaf = 0;
+  int32_t tensor = 0;          // tensor id (== SSA id)
+  int64_t src_off = 0;         // element offset in the leaf-data area
+  int32_t rank_src = 0;        // rank as given
+  int32_t rank = 0;            // unsliced rank
+  std::vector<int32_t> src_bit;     // canonical bit j -> source bit position
+  std::vector<int32_t> sl_src_bit;  // sliced axes: source bit position
+  std::vector<int32_t> sl_bit;      //              and slice-id bit
+  int32_t param = -1;
+};
+
+struct TensorPlan {
+  int32_t rank = 0;
+  ltn::IdSet idx;              // canonical order, lowest bit first
+  uint64_t off = 0;            // forward arena, per-slice byte offset
+  uint64_t goff = 0;           // grad arena: tensor
+  uint64_t gcot = 0;           // grad arena: its cotangent
+  int32_t producer = -1;       // step, -1 for leaves
+  int32_t consumer = -1;       // step, -1 for the root
+  uint64_t bytes() const { return 8ull << rank; }
+};
+
+struct StepPlan {
+  int32_t left = 0, right = 0, out = 0;
+  int32_t a = 0, b = 0;        // SSA ids of the row operand A and of B
+  int32_t a_is_left = 1;
+  int32_t m = 0, k = 0, n = 0;
+  int32_t kernel = 0;
+  uint64_t c_mask_a = 0;
+};
+
+struct ltn_plan_impl;
+
+struct ltn_plan {
+  // host description
+  int32_t L = 0;
+  int32_t n_indices = 0;
+  std::vector<int32_t> sliced;       // S, bit order
+  std::vector<int32_t> open_ids;
+  std::vector<LeafPlan> leaves;
+  std::vector<TensorPlan> tensors;   // by SSA id
+  std::vector<StepPlan> steps;
+  std::vector<int32_t> leaf_param;   // leaf -> u3 gate id
+  std::vector<float> leaf_data;      // complex64, leaves concatenated
+  int64_t leaf_elems = 0;
+  int32_t n_params = 0;              // number of angles (3 per u3 gate)
+  int32_t root = 0;
+  uint64_t out_mask = 0;             // output bits filled by the root
+  std::vector<std::pair<int32_t, int32_t>> out_sliced;  // (slice bit, output bit)
+  int32_t n_open = 0;
+  uint64_t arena = 0, garena = 0;    // per-slice bytes
+  ltn::BigSum macs;
+  double macs_d = 0;
+  ltn_options opt{};
+  // device side (runtime)
+  ltn_plan_impl* rt = nullptr;
+};
+
+void runtime_free(ltn_plan* p);
+void runtime_describe(const ltn_plan* p, ltn_plan_info* o);

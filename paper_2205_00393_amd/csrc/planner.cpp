@@ -1,0 +1,363 @@
+// Host planner: greedy contraction path, contraction tree and its costs
+// (Eq. (1), (2), (4)), the stem, lifetimes and the slice finder
+// (Algorithm 1) with a fix-up for off-stem tensors.
+//
+// Compiled with -ffp-contract=off: the greedy key is specified as a fixed
+// sequence of IEEE double operations so that any implementation of the same
+// rule makes the same choices.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <unordered_map>
+
+#include "common.h"
+
+namespace ltn {
+
+static uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  uint64_t z = x;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+static double keyed_uniform(uint64_t seed, uint64_t step, uint64_t a, uint64_t b) {
+  uint64_t h = splitmix64(seed);
+  h = splitmix64(h ^ step);
+  h = splitmix64(h ^ a);
+  h = splitmix64(h ^ b);
+  return (double)(h >> 11) * 0x1.0p-53;
+}
+
+static double pair_key(int rc, int ra, int rb, double alpha, double tau, double u) {
+  double t1 = std::ldexp(1.0, ra) + std::ldexp(1.0, rb);
+  double t2 = alpha * t1;
+  double base = std::ldexp(1.0, rc) - t2;
+  if (tau > 0.0) {
+    double f = tau * u;
+    if (base > 0.0)
+      base = base * (1.0 + f);
+    else
+      base = base * (1.0 - f);
+  }
+  return base;
+}
+
+std::vector<int32_t> greedy(const std::vector<IdSet>& leaves, const IdSet& exclude, double alpha,
+                            double tau, uint64_t seed) {
+  const int32_t L = (int32_t)leaves.size();
+  std::map<int32_t, IdSet> live;
+  std::unordered_map<int32_t, std::vector<int32_t>> owner;
+  for (int32_t i = 0; i < L; ++i) {
+    live[i] = set_minus(leaves[i], exclude);
+    for (int32_t x : live[i]) owner[x].push_back(i);
+  }
+  std::vector<int32_t> path;
+  int32_t nxt = L;
+  uint64_t step = 0;
+  while (live.size() > 1) {
+    bool have = false;
+    double bk = 0;
+    int32_t ba = 0, bb = 0;
+    for (auto& kv : owner) {
+      if (kv.second.size() != 2) continue;
+      int32_t a = std::min(kv.second[0], kv.second[1]), b = std::max(kv.second[0], kv.second[1]);
+      const IdSet& ia = live[a];
+      const IdSet& ib = live[b];
+      int shared = (int)set_and(ia, ib).size();
+      int rc = (int)ia.size() + (int)ib.size() - 2 * shared;
+      double u = tau > 0.0 ? keyed_uniform(seed, step, (uint64_t)a, (uint64_t)b) : 0.0;
+      double k = pair_key(rc, (int)ia.size(), (int)ib.size(), alpha, tau, u);
+      if (!have || k < bk || (k == bk && (a < ba || (a == ba && b < bb)))) {
+        have = true;
+        bk = k;
+        ba = a;
+        bb = b;
+      }
+    }
+    if (!have) {
+      auto it = live.begin();
+      ba = it->first;
+      ++it;
+      bb = it->first;
+    }
+    IdSet nw = set_xor(live[ba], live[bb]);
+    for (int32_t x : set_or(live[ba], live[bb])) {
+      auto& o = owner[x];
+      o.erase(std::remove_if(o.begin(), o.end(), [&](int32_t u) { return u == ba || u == bb; }),
+              o.end());
+      if (set_has(nw, x))
+        o.push_back(nxt);
+      else if (o.empty())
+        owner.erase(x);
+    }
+    live.erase(ba);
+    live.erase(bb);
+    live[nxt] = nw;
+    path.push_back(ba);
+    path.push_back(bb);
+    ++nxt;
+    ++step;
+  }
+  return path;
+}
+
+Tree Tree::build(const std::vector<IdSet>& leaves, const int32_t* path) {
+  Tree t;
+  t.L = (int32_t)leaves.size();
+  t.sets = leaves;
+  t.kids.assign(t.L, {-1, -1});
+  int32_t n = 2 * t.L - 1;
+  t.parent.assign(n, -1);
+  std::vector<char> used(n, 0);
+  for (int32_t k = 0; k + 1 < t.L; ++k) {
+    int32_t a = path[2 * k], b = path[2 * k + 1], v = t.L + k;
+    require(a >= 0 && b >= 0 && a < v && b < v && a != b,
+            "path step " + std::to_string(k) + " names an invalid SSA id");
+    require(!used[a] && !used[b], "path step " + std::to_string(k) + " reuses a consumed tensor");
+    used[a] = used[b] = 1;
+    t.sets.push_back(set_xor(t.sets[a], t.sets[b]));
+    t.kids.push_back({a, b});
+    t.parent[a] = v;
+    t.parent[b] = v;
+  }
+  return t;
+}
+
+BigSum Tree::cost() const {
+  BigSum s;
+  for (int32_t v = L; v < (int32_t)sets.size(); ++v) s.add_pow2((int)node_set(v).size());
+  return s;
+}
+
+BigSum Tree::sliced_cost(const IdSet& S) const {
+  BigSum s;
+  for (int32_t v = L; v < (int32_t)sets.size(); ++v) {
+    IdSet sv = node_set(v);
+    int e = (int)sv.size() + (int)S.size() - (int)set_and(S, sv).size();
+    s.add_pow2(e);
+  }
+  return s;
+}
+
+int Tree::space(const IdSet& S) const {
+  int m = 0;
+  for (auto& s : sets) m = std::max(m, (int)set_minus(s, S).size());
+  return m;
+}
+
+static void big_add(BigSum& a, const BigSum& b) {
+  if (a.w.size() < b.w.size()) a.w.resize(b.w.size(), 0);
+  uint64_t carry = 0;
+  for (size_t i = 0; i < a.w.size(); ++i) {
+    uint64_t bi = i < b.w.size() ? b.w[i] : 0;
+    uint64_t s = a.w[i] + bi;
+    uint64_t c1 = s < a.w[i];
+    uint64_t s2 = s + carry;
+    uint64_t c2 = s2 < s;
+    a.w[i] = s2;
+    carry = c1 | c2;
+  }
+  if (carry) a.w.push_back(1);
+}
+
+std::vector<int32_t> Tree::stem() const {
+  int32_t n = (int32_t)sets.size();
+  std::vector<BigSum> best(n), sub(n);
+  for (int32_t v = L; v < n; ++v) {
+    auto [a, b] = kids[v];
+    BigSum c;
+    c.add_pow2((int)node_set(v).size());
+    BigSum bv = c;
+    big_add(bv, best[a].compare(best[b]) >= 0 ? best[a] : best[b]);
+    best[v] = bv;
+    BigSum sv = c;
+    big_add(sv, sub[a]);
+    big_add(sv, sub[b]);
+    sub[v] = sv;
+  }
+  std::vector<int32_t> out{root()};
+  int32_t v = root();
+  while (v >= L) {
+    auto [a, b] = kids[v];
+    // larger best, then larger subtree cost, then smaller id
+    int c = best[a].compare(best[b]);
+    if (c == 0) c = sub[a].compare(sub[b]);
+    int32_t pick = c > 0 ? a : (c < 0 ? b : std::min(a, b));
+    out.push_back(pick);
+    v = pick;
+  }
+  std::reverse(out.begin(), out.end());
+  return out;
+}
+
+std::vector<int32_t> slice_finder(const std::vector<IdSet>& leaves, const int32_t* path, int t,
+                                  const std::vector<int32_t>& pre) {
+  std::vector<int32_t> S(pre.begin(), pre.end());
+  if (t < 0) return S;
+  IdSet ps(pre.begin(), pre.end());
+  std::sort(ps.begin(), ps.end());
+  std::vector<IdSet> lv(leaves.size());
+  for (size_t i = 0; i < leaves.size(); ++i) lv[i] = set_minus(leaves[i], ps);
+  Tree tree = Tree::build(lv, path);
+  const int32_t n = (int32_t)tree.sets.size();
+  std::unordered_map<int32_t, int> whole;
+  for (auto& s : tree.sets)
+    for (int32_t x : s) whole[x]++;
+  IdSet inS;  // sorted, the indices added here
+  auto dim = [&](int32_t v) { return (int)set_minus(tree.sets[v], inS).size(); };
+  auto add = [&](int32_t x) {
+    S.push_back(x);
+    inS.insert(std::lower_bound(inS.begin(), inS.end(), x), x);
+  };
+  std::vector<int32_t> M = tree.stem();
+  auto lifetimes = [&]() {
+    std::unordered_map<int32_t, int> lf;
+    for (int32_t v : M)
+      for (int32_t x : tree.sets[v]) lf[x]++;
+    return lf;
+  };
+  auto lf = lifetimes();
+  while (!M.empty()) {
+    int32_t sT = dim(M.front()) < dim(M.back()) ? M.front() : M.back();
+    int need = dim(sT) - t;
+    if (need > 0) {
+      IdSet cand = set_minus(tree.sets[sT], inS);
+      std::sort(cand.begin(), cand.end(), [&](int32_t x, int32_t y) {
+        if (lf[x] != lf[y]) return lf[x] > lf[y];
+        if (whole[x] != whole[y]) return whole[x] > whole[y];
+        return x < y;
+      });
+      for (int i = 0; i < need; ++i) add(cand[i]);
+    }
+    std::vector<int32_t> keep;
+    for (int32_t v : M)
+      if (dim(v) > t) keep.push_back(v);
+    M.swap(keep);
+    lf = lifetimes();
+  }
+  for (int32_t v = 0; v < n; ++v) {
+    while (dim(v) > t) {
+      IdSet cand = set_minus(tree.sets[v], inS);
+      int32_t best = cand[0];
+      for (int32_t x : cand)
+        if (whole[x] > whole[best] || (whole[x] == whole[best] && x < best)) best = x;
+      add(best);
+    }
+  }
+  return S;
+}
+
+}  // namespace ltn
+
+using namespace ltn;
+
+extern "C" ltn_status ltn_greedy_path(const ltn_network* net, const int32_t* exclude,
+                                      int32_t n_exclude, double alpha, double tau, uint64_t seed,
+                                      int32_t* path_out) {
+  return guarded([&] {
+    Net n = Net::from_abi(net, false);
+    require(path_out != nullptr, "path_out is NULL");
+    require(n_exclude >= 0 && (n_exclude == 0 || exclude), "bad exclude list");
+    IdSet ex(exclude, exclude + n_exclude);
+    std::sort(ex.begin(), ex.end());
+    auto p = greedy(n.sets, ex, alpha, tau, seed);
+    std::copy(p.begin(), p.end(), path_out);
+  });
+}
+
+extern "C" ltn_status ltn_tree_costs(const ltn_network* net, const int32_t* path, const int32_t* S,
+                                     int32_t n_sliced, ltn_costs* out) {
+  return guarded([&] {
+    Net n = Net::from_abi(net, false);
+    require(path && out, "NULL argument");
+    require(n_sliced >= 0 && (n_sliced == 0 || S), "bad slicing set");
+    Tree t = Tree::build(n.sets, path);
+    IdSet s(S, S + n_sliced);
+    std::sort(s.begin(), s.end());
+    BigSum c = t.cost(), cs = t.sliced_cost(s);
+    out->log2_cost = c.log2();
+    out->log2_sliced = cs.log2();
+    out->overhead = std::exp2(out->log2_sliced - out->log2_cost);
+    out->space_log2 = t.space(s);
+    out->space_log2_unsliced = t.space({});
+    c.to_words(out->cost_words, 4);
+    cs.to_words(out->sliced_words, 4);
+    out->stem_len = (int32_t)t.stem().size();
+  });
+}
+
+extern "C" ltn_status ltn_tree_stem(const ltn_network* net, const int32_t* path, int32_t* stem_out,
+                                    int32_t cap, int32_t* len) {
+  return guarded([&] {
+    Net n = Net::from_abi(net, false);
+    require(path && stem_out && len, "NULL argument");
+    auto st = Tree::build(n.sets, path).stem();
+    require((int32_t)st.size() <= cap, "stem_out too small", LTN_E_NOMEM);
+    std::copy(st.begin(), st.end(), stem_out);
+    *len = (int32_t)st.size();
+  });
+}
+
+extern "C" ltn_status ltn_slice_finder(const ltn_network* net, const int32_t* path, int32_t t,
+                                       const int32_t* pre, int32_t n_pre, int32_t* S_out,
+                                       int32_t cap, int32_t* n_sliced) {
+  return guarded([&] {
+    Net n = Net::from_abi(net, false);
+    require(path && S_out && n_sliced, "NULL argument");
+    require(n_pre >= 0 && (n_pre == 0 || pre), "bad pre list");
+    std::vector<int32_t> p(pre, pre + n_pre);
+    auto S = slice_finder(n.sets, path, t, p);
+    require((int32_t)S.size() <= cap, "S_out too small", LTN_E_NOMEM);
+    std::copy(S.begin(), S.end(), S_out);
+    *n_sliced = (int32_t)S.size();
+  });
+}
+
+extern "C" ltn_status ltn_path_search(const ltn_network* net, int32_t t, const int32_t* pre,
+                                      int32_t n_pre, const ltn_search_opts* o, int32_t* path_out,
+                                      int32_t* S_out, int32_t cap, int32_t* n_sliced,
+                                      int32_t* best_trial) {
+  return guarded([&] {
+    Net n = Net::from_abi(net, false);
+    require(o && path_out && S_out && n_sliced, "NULL argument");
+    require(o->n_alpha >= 1 && o->alphas && o->n_tau >= 1 && o->taus && o->n_seeds >= 1,
+            "empty search grid");
+    require(n_pre >= 0 && (n_pre == 0 || pre), "bad pre list");
+    std::vector<int32_t> p(pre, pre + n_pre);
+    IdSet ex(p.begin(), p.end());
+    std::sort(ex.begin(), ex.end());
+    bool have = false;
+    BigSum bc;
+    size_t bs = 0;
+    int32_t btrial = -1, trial = 0;
+    std::vector<int32_t> bpath, bS;
+    for (int ia = 0; ia < o->n_alpha; ++ia)
+      for (int it = 0; it < o->n_tau; ++it) {
+        int seeds = o->taus[it] > 0.0 ? o->n_seeds : 1;
+        for (int sd = 0; sd < seeds; ++sd, ++trial) {
+          auto path = greedy(n.sets, ex, o->alphas[ia], o->taus[it], o->seed_base + (uint64_t)sd);
+          auto S = slice_finder(n.sets, path.data(), t, p);
+          Tree tr = Tree::build(n.sets, path.data());
+          IdSet ss(S.begin(), S.end());
+          std::sort(ss.begin(), ss.end());
+          BigSum c = tr.sliced_cost(ss);
+          int cmp = have ? c.compare(bc) : -1;
+          if (!have || cmp < 0 || (cmp == 0 && S.size() < bs)) {
+            have = true;
+            bc = c;
+            bs = S.size();
+            btrial = trial;
+            bpath = path;
+            bS = S;
+          }
+        }
+      }
+    require((int32_t)bS.size() <= cap, "S_out too small", LTN_E_NOMEM);
+    std::copy(bpath.begin(), bpath.end(), path_out);
+    std::copy(bS.begin(), bS.end(), S_out);
+    *n_sliced = (int32_t)bS.size();
+    if (best_trial) *best_trial = btrial;
+  });
+}

@@ -1,0 +1,642 @@
+// Device side of a plan: workspace layout, batch execution (leaf gather ->
+// contraction steps -> FP64 slice sum), hipGraph capture and replay, the
+// adjoint sweep for gradients, tile autotuning and per-step profiling.
+//
+// Everything runs on the stream given to ltn_bind; the library allocates no
+// device memory of its own (the caller's workspace holds leaf data,
+// descriptors, slice ids, the per-slice arenas and gradient accumulators).
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+
+#include "kernels.h"
+#include "plan.h"
+
+using namespace ltn;
+
+#define HIPCHECK(x)                                                                     \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess)                                                               \
+      fail(LTN_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_) + " (" +         \
+                          std::to_string((int)e_) + ")");                               \
+  } while (0)
+
+struct Layout {
+  size_t leafdata, gd_fwd, gd_grad, gd_gcot, pl, angles, leafgrad, ids, scales, arena, total;
+};
+
+struct ltn_plan_impl {
+  hipStream_t st = nullptr;
+  hipStream_t cap = nullptr;  // capture stream (the null stream cannot be captured)
+  char* ws = nullptr;
+  size_t bytes = 0;
+  int grad = 0;
+  int B = 0;
+  Layout lay{};
+  int n_pl = 0;
+  int max_leaf_elems = 1;
+  std::vector<GatherDesc> gd_fwd, gd_grad, gd_gcot;
+  std::vector<ParamLeaf> pl;
+  std::vector<int32_t> sl_bits, out_bits;
+  std::vector<int> cfg;  // per step: gemm config or -1
+  std::vector<int> tk;   // per step: generic threads per output
+  std::vector<char> swap;
+  std::vector<char> needs_grad;
+  hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
+  hipGraph_t graph_src[3] = {nullptr, nullptr, nullptr};
+  std::vector<uint64_t> host_ids;
+};
+
+namespace {
+
+size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+Layout layout(const ltn_plan* p, int B, int grad) {
+  Layout l{};
+  size_t o = 0;
+  int npl = 0;
+  for (auto& lp : p->leaves) npl += lp.param >= 0;
+  l.leafdata = o;
+  o = al(o + (size_t)p->leaf_elems * 8);
+  l.gd_fwd = o;
+  o = al(o + p->leaves.size() * sizeof(GatherDesc));
+  l.gd_grad = o;
+  o = al(o + (grad ? p->leaves.size() * sizeof(GatherDesc) : 0));
+  l.gd_gcot = o;
+  o = al(o + (grad ? p->leaves.size() * sizeof(GatherDesc) : 0));
+  l.pl = o;
+  o = al(o + (size_t)npl * sizeof(ParamLeaf));
+  l.angles = o;
+  o = al(o + (size_t)p->n_params * sizeof(double));
+  l.leafgrad = o;
+  o = al(o + (size_t)npl * 8 * sizeof(double));
+  l.ids = o;
+  o = al(o + (size_t)B * 8);
+  l.scales = o;
+  o = al(o + (size_t)B * p->tensors.size() * 4);
+  l.arena = o;
+  o = al(o + (size_t)B * (grad ? p->garena : p->arena));
+  l.total = o;
+  return l;
+}
+
+ltn_plan_impl& rt(ltn_plan* p) {
+  if (!p || !p->rt || !p->rt->ws) fail(LTN_E_STATE, "plan is not bound (call ltn_bind first)");
+  return *p->rt;
+}
+
+float2* arena_ptr(ltn_plan* p, uint64_t off_bytes) {
+  auto& r = *p->rt;
+  return reinterpret_cast<float2*>(r.ws + r.lay.arena + off_bytes * (uint64_t)r.B);
+}
+
+int default_cfg(int m, int k, int n) {
+  for (int c = 0; c < 8; ++c)
+    if (gemm_config_fits(c, m, k, n)) return c;
+  return -1;
+}
+
+int default_tk(int k, uint64_t outs) {
+  int tk = k <= 3 ? 1 : (k <= 6 ? 8 : 64);
+  if (outs < (1u << 16) && k >= 3) tk = std::max(tk, 8);
+  if (outs < (1u << 12) && k >= 5) tk = 64;
+  return tk;
+}
+
+void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena) {
+  auto& r = *p->rt;
+  const StepPlan& sp = p->steps[s];
+  const TensorPlan &ta = p->tensors[sp.a], &tb = p->tensors[sp.b], &tc = p->tensors[sp.out];
+  float2* A = arena_ptr(p, gradarena ? ta.goff : ta.off);
+  float2* B = arena_ptr(p, gradarena ? tb.goff : tb.off);
+  float2* C = arena_ptr(p, gradarena ? tc.goff : tc.off);
+  const uint64_t cm = sp.c_mask_a, full = (sp.m + sp.n) >= 64 ? ~0ull : ((1ull << (sp.m + sp.n)) - 1);
+  if (r.cfg[s] >= 0) {
+    GemmDesc d{};
+    bool sw = r.swap[s];
+    d.A = sw ? B : A;
+    d.B = sw ? A : B;
+    d.C = C;
+    d.sA = int64_t(1) << (sw ? tb.rank : ta.rank);
+    d.sB = int64_t(1) << (sw ? ta.rank : tb.rank);
+    d.sC = int64_t(1) << tc.rank;
+    d.m = sw ? sp.n : sp.m;
+    d.n = sw ? sp.m : sp.n;
+    d.k = sp.k;
+    d.cmask = sw ? (~cm & full) : cm;
+    d.nb = nb;
+    d.cfg = r.cfg[s];
+    launch_cgemm(d, LTN_C64, r.st);
+  } else {
+    GenericDesc g{};
+    g.P = A;
+    g.Q = B;
+    g.out = C;
+    g.sP = int64_t(1) << ta.rank;
+    g.sQ = int64_t(1) << tb.rank;
+    g.sO = int64_t(1) << tc.rank;
+    g.xb = sp.m;
+    g.yb = sp.n;
+    g.zb = sp.k;
+    g.px = ((1ull << sp.m) - 1) << sp.k;
+    g.pz = (1ull << sp.k) - 1;
+    g.qy = ((1ull << sp.n) - 1) << sp.k;
+    g.qz = (1ull << sp.k) - 1;
+    g.ox = cm;
+    g.oy = ~cm & full;
+    g.nb = nb;
+    launch_generic(g, r.tk[s], r.st);
+  }
+}
+
+void enqueue_forward(ltn_plan* p, int nb, bool gradarena) {
+  auto& r = *p->rt;
+  const GatherDesc* gd = reinterpret_cast<const GatherDesc*>(r.ws + (gradarena ? r.lay.gd_grad : r.lay.gd_fwd));
+  launch_gather(gd, (int)p->leaves.size(), r.max_leaf_elems,
+                reinterpret_cast<const float2*>(r.ws + r.lay.leafdata), arena_ptr(p, 0),
+                reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids), nb, r.st);
+  for (int s = 0; s < (int)p->steps.size(); ++s) enqueue_step(p, s, nb, gradarena);
+}
+
+void enqueue_reduce(ltn_plan* p, int nb, bool gradarena, double* out) {
+  auto& r = *p->rt;
+  const TensorPlan& root = p->tensors[p->root];
+  launch_reduce(arena_ptr(p, gradarena ? root.goff : root.off), root.rank, p->out_mask,
+                r.sl_bits.data(), r.out_bits.data(), (int)r.sl_bits.size(),
+                reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids), nb, out, r.st);
+}
+
+void set_ids(ltn_plan* p, const uint64_t* ids, uint64_t base, int n, bool range) {
+  auto& r = *p->rt;
+  uint64_t* d = reinterpret_cast<uint64_t*>(r.ws + r.lay.ids);
+  if (range)
+    launch_set_range(d, base, n, r.st);
+  else
+    launch_set_ids(d, ids, n, r.st);
+}
+
+void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) fail(LTN_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+void run_batch(ltn_plan* p, int nb, int mode, double* out) {
+  auto& r = *p->rt;
+  if (nb == r.B) {
+    if (!r.graph[mode]) {
+      if (!r.cap) HIPCHECK(hipStreamCreateWithFlags(&r.cap, hipStreamNonBlocking));
+      hipGraph_t g;
+      hipStream_t bound = r.st;
+      r.st = r.cap;
+      hipError_t e = hipStreamBeginCapture(r.cap, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        try {
+          enqueue_forward(p, nb, false);
+        } catch (...) {
+          r.st = bound;
+          (void)hipStreamEndCapture(r.cap, &g);
+          throw;
+        }
+        e = hipStreamEndCapture(r.cap, &g);
+      }
+      r.st = bound;
+      if (e != hipSuccess) fail(LTN_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+      HIPCHECK(hipGraphInstantiate(&r.graph[mode], g, nullptr, nullptr, 0));
+      r.graph_src[mode] = g;
+    }
+    HIPCHECK(hipGraphLaunch(r.graph[mode], r.st));
+  } else {
+    enqueue_forward(p, nb, false);
+  }
+  enqueue_reduce(p, nb, false, out);
+  check_launch();
+}
+
+void check_mode(int mode) {
+  require(mode == LTN_C64 || mode == LTN_SPLIT_F16 || mode == LTN_SPLIT_BF16, "unknown mode");
+  if (mode != LTN_C64) fail(LTN_E_UNSUPPORTED, "split precision is not available in this build");
+}
+
+}  // namespace
+
+void runtime_describe(const ltn_plan* p, ltn_plan_info* o) {
+  if (p->rt) o->batch = p->rt->B;
+  o->const_bytes = layout(p, 0, 0).total;
+}
+
+void runtime_free(ltn_plan* p) {
+  if (!p->rt) return;
+  for (int m = 0; m < 3; ++m) {
+    if (p->rt->graph[m]) (void)hipGraphExecDestroy(p->rt->graph[m]);
+    if (p->rt->graph_src[m]) (void)hipGraphDestroy(p->rt->graph_src[m]);
+  }
+  if (p->rt->cap) (void)hipStreamDestroy(p->rt->cap);
+  delete p->rt;
+  p->rt = nullptr;
+}
+
+extern "C" ltn_status ltn_workspace_size(const ltn_plan* p, int32_t batch, int32_t grad,
+                                         size_t* bytes) {
+  return guarded([&] {
+    require(p && bytes, "NULL argument");
+    require(batch >= 1, "batch must be >= 1");
+    *bytes = layout(p, batch, grad).total;
+  });
+}
+
+extern "C" ltn_status ltn_bind(ltn_plan* p, void* d_ws, size_t bytes, int32_t grad, void* stream) {
+  return guarded([&] {
+    require(p != nullptr, "plan is NULL");
+    require(d_ws != nullptr, "workspace is NULL");
+    require(((uintptr_t)d_ws & 255) == 0, "workspace must be 256-byte aligned");
+    // grid.y limit of the gather; no batch larger than the slice count
+    int B = std::min(p->opt.batch > 0 ? p->opt.batch : 4096, 4096);
+    if (p->sliced.size() < 12) B = std::min(B, 1 << p->sliced.size());
+    while (B > 1 && layout(p, B, grad).total > bytes) {
+      size_t per = grad ? p->garena : p->arena;
+      size_t fixed = layout(p, 0, grad).total;
+      size_t fit = bytes > fixed ? (bytes - fixed) / (per + 8 + 4 * p->tensors.size() + 512) : 0;
+      B = (int)std::max<size_t>(1, std::min<size_t>(fit, (size_t)B - 1));
+      if (layout(p, B, grad).total <= bytes) break;
+    }
+    if (layout(p, B, grad).total > bytes)
+      fail(LTN_E_NOMEM, "workspace of " + std::to_string(bytes) + " bytes is below the " +
+                            std::to_string(layout(p, 1, grad).total) + " needed for one slice");
+    runtime_free(p);
+    auto r = new ltn_plan_impl();
+    p->rt = r;
+    r->st = reinterpret_cast<hipStream_t>(stream);
+    r->ws = reinterpret_cast<char*>(d_ws);
+    r->bytes = bytes;
+    r->grad = grad;
+    r->B = B;
+    r->lay = layout(p, B, grad);
+    // descriptors
+    int gi = 0;
+    for (auto& lp : p->leaves) {
+      require(lp.rank_src <= kMaxLeafRank, "leaf rank above 32 is not supported");
+      GatherDesc g{};
+      g.src_off = lp.src_off;
+      g.rank = lp.rank;
+      g.nsl = (int32_t)lp.sl_bit.size();
+      for (int j = 0; j < lp.rank; ++j) g.src_bit[j] = (int8_t)lp.src_bit[j];
+      for (int j = 0; j < g.nsl; ++j) {
+        g.sl_src_bit[j] = (int8_t)lp.sl_src_bit[j];
+        g.sl_bit[j] = (int8_t)lp.sl_bit[j];
+      }
+      const TensorPlan& t = p->tensors[lp.tensor];
+      g.dst_off = (int64_t)(t.off * (uint64_t)B / 8);
+      r->gd_fwd.push_back(g);
+      g.dst_off = (int64_t)(t.goff * (uint64_t)B / 8);
+      r->gd_grad.push_back(g);
+      g.dst_off = (int64_t)(t.gcot * (uint64_t)B / 8);
+      r->gd_gcot.push_back(g);
+      r->max_leaf_elems = std::max(r->max_leaf_elems, 1 << lp.rank);
+      if (lp.param >= 0) r->pl.push_back(ParamLeaf{lp.src_off, lp.param, gi});
+      ++gi;
+    }
+    r->n_pl = (int)r->pl.size();
+    for (auto& pr : p->out_sliced) {
+      r->sl_bits.push_back(pr.first);
+      r->out_bits.push_back(pr.second);
+    }
+    require(r->sl_bits.size() <= 32, "more than 32 sliced open indices");
+    // kernel choice per step
+    for (auto& sp : p->steps) {
+      int c = -1;
+      bool sw = false;
+      if (sp.kernel == LTN_K_MFMA) {
+        sw = (sp.c_mask_a & 1) != 0;  // put the output's lowest bits on the MFMA columns
+        c = sw ? default_cfg(sp.n, sp.k, sp.m) : default_cfg(sp.m, sp.k, sp.n);
+        if (c < 0) {
+          sw = !sw;
+          c = sw ? default_cfg(sp.n, sp.k, sp.m) : default_cfg(sp.m, sp.k, sp.n);
+        }
+      }
+      r->cfg.push_back(c);
+      r->swap.push_back(sw);
+      r->tk.push_back(default_tk(sp.k, (1ull << (sp.m + sp.n)) * (uint64_t)B));
+    }
+    r->needs_grad.assign(p->tensors.size(), 0);
+    for (size_t v = 0; v < p->tensors.size(); ++v) {
+      if ((int)v < p->L)
+        r->needs_grad[v] = p->leaves[v].param >= 0;
+      else {
+        const StepPlan& sp = p->steps[v - p->L];
+        r->needs_grad[v] = r->needs_grad[sp.left] || r->needs_grad[sp.right];
+      }
+    }
+    // uploads (host vectors live in the plan / impl; synchronised below)
+    HIPCHECK(hipMemcpyAsync(r->ws + r->lay.leafdata, p->leaf_data.data(), (size_t)p->leaf_elems * 8,
+                            hipMemcpyHostToDevice, r->st));
+    HIPCHECK(hipMemcpyAsync(r->ws + r->lay.gd_fwd, r->gd_fwd.data(), r->gd_fwd.size() * sizeof(GatherDesc),
+                            hipMemcpyHostToDevice, r->st));
+    if (grad) {
+      HIPCHECK(hipMemcpyAsync(r->ws + r->lay.gd_grad, r->gd_grad.data(),
+                              r->gd_grad.size() * sizeof(GatherDesc), hipMemcpyHostToDevice, r->st));
+      HIPCHECK(hipMemcpyAsync(r->ws + r->lay.gd_gcot, r->gd_gcot.data(),
+                              r->gd_gcot.size() * sizeof(GatherDesc), hipMemcpyHostToDevice, r->st));
+    }
+    if (r->n_pl)
+      HIPCHECK(hipMemcpyAsync(r->ws + r->lay.pl, r->pl.data(), r->pl.size() * sizeof(ParamLeaf),
+                              hipMemcpyHostToDevice, r->st));
+    HIPCHECK(hipStreamSynchronize(r->st));
+  });
+}
+
+static ltn_status execute_impl(ltn_plan* p, const uint64_t* ids, uint64_t begin, uint64_t n,
+                               bool range, int32_t mode, void* d_out) {
+  return guarded([&] {
+    auto& r = rt(p);
+    check_mode(mode);
+    require(d_out != nullptr, "d_out is NULL");
+    const int ns = (int)p->sliced.size();
+    const uint64_t lim = ns >= 64 ? ~0ull : (1ull << ns);
+    if (range) {
+      require(begin <= n, "range end before begin");
+      require(n <= lim, "slice range beyond 2^|S|");
+      n = n - begin;
+    } else {
+      require(n == 0 || ids != nullptr, "slice_ids is NULL");
+      for (uint64_t i = 0; i < n; ++i)
+        require(ids[i] < lim, "slice id " + std::to_string(ids[i]) + " is not below 2^|S|");
+    }
+    for (uint64_t off = 0; off < n; off += (uint64_t)r.B) {
+      int nb = (int)std::min<uint64_t>((uint64_t)r.B, n - off);
+      set_ids(p, range ? nullptr : ids + off, begin + off, nb, range);
+      run_batch(p, nb, mode, reinterpret_cast<double*>(d_out));
+    }
+  });
+}
+
+extern "C" ltn_status ltn_execute(ltn_plan* p, const uint64_t* ids, uint64_t n, int32_t mode,
+                                  void* d_out) {
+  return execute_impl(p, ids, 0, n, false, mode, d_out);
+}
+
+extern "C" ltn_status ltn_execute_range(ltn_plan* p, uint64_t begin, uint64_t end, int32_t mode,
+                                        void* d_out) {
+  return execute_impl(p, nullptr, begin, end, true, mode, d_out);
+}
+
+extern "C" ltn_status ltn_set_params(ltn_plan* p, const double* d_angles) {
+  return guarded([&] {
+    auto& r = rt(p);
+    require(r.n_pl == 0 || d_angles != nullptr, "d_angles is NULL");
+    if (r.n_pl == 0) return;
+    double* ang = reinterpret_cast<double*>(r.ws + r.lay.angles);
+    HIPCHECK(hipMemcpyAsync(ang, d_angles, (size_t)p->n_params * sizeof(double),
+                            hipMemcpyDeviceToDevice, r.st));
+    launch_u3_build(reinterpret_cast<const ParamLeaf*>(r.ws + r.lay.pl), r.n_pl, ang,
+                    reinterpret_cast<float2*>(r.ws + r.lay.leafdata), r.st);
+    check_launch();
+  });
+}
+
+extern "C" ltn_status ltn_execute_grad(ltn_plan* p, const uint64_t* ids, uint64_t n, int32_t mode,
+                                       const void* d_cot, void* d_out, double* d_angle_grad) {
+  return guarded([&] {
+    auto& r = rt(p);
+    check_mode(mode);
+    require(r.grad, "plan was bound without gradient workspace");
+    require(d_cot && d_angle_grad, "NULL argument");
+    require(n == 0 || ids, "slice_ids is NULL");
+    const int ns = (int)p->sliced.size();
+    const uint64_t lim = ns >= 64 ? ~0ull : (1ull << ns);
+    for (uint64_t i = 0; i < n; ++i) require(ids[i] < lim, "slice id is not below 2^|S|");
+    double* lg = reinterpret_cast<double*>(r.ws + r.lay.leafgrad);
+    launch_fill_zero(lg, al((size_t)r.n_pl * 64), r.st);
+    const GatherDesc* gcot = reinterpret_cast<const GatherDesc*>(r.ws + r.lay.gd_gcot);
+    const uint64_t* dids = reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids);
+    for (uint64_t off = 0; off < n; off += (uint64_t)r.B) {
+      int nb = (int)std::min<uint64_t>((uint64_t)r.B, n - off);
+      set_ids(p, ids + off, 0, nb, false);
+      enqueue_forward(p, nb, true);
+      if (d_out) enqueue_reduce(p, nb, true, reinterpret_cast<double*>(d_out));
+      const TensorPlan& root = p->tensors[p->root];
+      launch_root_cotangent(reinterpret_cast<const double*>(d_cot), root.rank, p->out_mask,
+                            r.sl_bits.data(), r.out_bits.data(), (int)r.sl_bits.size(), dids, nb,
+                            arena_ptr(p, root.gcot), r.st);
+      for (int s = (int)p->steps.size() - 1; s >= 0; --s) {
+        const StepPlan& sp = p->steps[s];
+        if (!r.needs_grad[sp.out]) continue;
+        const TensorPlan &ta = p->tensors[sp.a], &tb = p->tensors[sp.b], &tc = p->tensors[sp.out];
+        const uint64_t cm = sp.c_mask_a, full = (1ull << (sp.m + sp.n)) - 1;
+        if (r.needs_grad[sp.a]) {
+          GenericDesc g{};
+          g.P = arena_ptr(p, tc.gcot);
+          g.Q = arena_ptr(p, tb.goff);
+          g.out = arena_ptr(p, ta.gcot);
+          g.sP = int64_t(1) << tc.rank;
+          g.sQ = int64_t(1) << tb.rank;
+          g.sO = int64_t(1) << ta.rank;
+          g.xb = sp.m;
+          g.yb = sp.k;
+          g.zb = sp.n;
+          g.px = cm;
+          g.pz = ~cm & full;
+          g.qy = (1ull << sp.k) - 1;
+          g.qz = ((1ull << sp.n) - 1) << sp.k;
+          g.ox = ((1ull << sp.m) - 1) << sp.k;
+          g.oy = (1ull << sp.k) - 1;
+          g.conjQ = 1;
+          g.nb = nb;
+          launch_generic(g, default_tk(sp.n, (1ull << (sp.m + sp.k)) * (uint64_t)nb), r.st);
+        }
+        if (r.needs_grad[sp.b]) {
+          GenericDesc g{};
+          g.P = arena_ptr(p, tc.gcot);
+          g.Q = arena_ptr(p, ta.goff);
+          g.out = arena_ptr(p, tb.gcot);
+          g.sP = int64_t(1) << tc.rank;
+          g.sQ = int64_t(1) << ta.rank;
+          g.sO = int64_t(1) << tb.rank;
+          g.xb = sp.n;
+          g.yb = sp.k;
+          g.zb = sp.m;
+          g.px = ~cm & full;
+          g.pz = cm;
+          g.qy = (1ull << sp.k) - 1;
+          g.qz = ((1ull << sp.m) - 1) << sp.k;
+          g.ox = ((1ull << sp.n) - 1) << sp.k;
+          g.oy = (1ull << sp.k) - 1;
+          g.conjQ = 1;
+          g.nb = nb;
+          launch_generic(g, default_tk(sp.m, (1ull << (sp.n + sp.k)) * (uint64_t)nb), r.st);
+        }
+      }
+      launch_leaf_cot_accumulate(reinterpret_cast<const ParamLeaf*>(r.ws + r.lay.pl), r.n_pl, gcot,
+                                 arena_ptr(p, 0), dids, nb, lg, r.st);
+      check_launch();
+    }
+    launch_u3_adjoint(reinterpret_cast<const ParamLeaf*>(r.ws + r.lay.pl), r.n_pl,
+                      reinterpret_cast<const double*>(r.ws + r.lay.angles), lg, d_angle_grad, r.st);
+    check_launch();
+  });
+}
+
+namespace {
+
+std::string tune_key(int mode, const StepPlan& sp, int B) {
+  std::ostringstream o;
+  o << "m" << mode << "_" << sp.m << "_" << sp.k << "_" << sp.n << "_" << (sp.c_mask_a & 1) << "_b" << B;
+  return o.str();
+}
+
+std::map<std::string, std::pair<int, int>> read_cache(const char* path) {
+  std::map<std::string, std::pair<int, int>> c;
+  if (!path) return c;
+  std::ifstream f(path);
+  if (!f) return c;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  std::string s = ss.str();
+  // entries look like "key": [a, b]
+  size_t pos = 0;
+  while ((pos = s.find('"', pos)) != std::string::npos) {
+    size_t e = s.find('"', pos + 1);
+    if (e == std::string::npos) break;
+    std::string key = s.substr(pos + 1, e - pos - 1);
+    size_t lb = s.find('[', e), rb = s.find(']', e);
+    if (lb == std::string::npos || rb == std::string::npos) break;
+    int a = 0, b = 0;
+    if (sscanf(s.c_str() + lb + 1, "%d , %d", &a, &b) == 2) c[key] = {a, b};
+    pos = rb + 1;
+  }
+  return c;
+}
+
+void write_cache(const char* path, const std::map<std::string, std::pair<int, int>>& c) {
+  if (!path) return;
+  std::ofstream f(path);
+  f << "{\n";
+  size_t i = 0;
+  for (auto& kv : c)
+    f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]"
+      << (++i < c.size() ? ",\n" : "\n");
+  f << "}\n";
+}
+
+float time_step(ltn_plan* p, int s, int reps) {
+  auto& r = *p->rt;
+  hipEvent_t a, b;
+  HIPCHECK(hipEventCreate(&a));
+  HIPCHECK(hipEventCreate(&b));
+  enqueue_step(p, s, r.B, false);  // untimed warm-up launch
+  HIPCHECK(hipEventRecord(a, r.st));
+  for (int i = 0; i < reps; ++i) enqueue_step(p, s, r.B, false);
+  HIPCHECK(hipEventRecord(b, r.st));
+  HIPCHECK(hipEventSynchronize(b));
+  float ms = 0;
+  HIPCHECK(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  check_launch();
+  return ms / reps;
+}
+
+void drop_graphs(ltn_plan* p) {
+  auto& r = *p->rt;
+  for (int m = 0; m < 3; ++m) {
+    if (r.graph[m]) (void)hipGraphExecDestroy(r.graph[m]);
+    if (r.graph_src[m]) (void)hipGraphDestroy(r.graph_src[m]);
+    r.graph[m] = nullptr;
+    r.graph_src[m] = nullptr;
+  }
+}
+
+}  // namespace
+
+// Candidates: every MFMA tile configuration that fits the step in either
+// operand role, and the generic kernel with 1, 8 or 64 threads per output.
+// Encoded as (cfg, swap) with cfg = -1 - tk for the generic kernel.
+extern "C" ltn_status ltn_autotune(ltn_plan* p, int32_t mode, const char* cache_path) {
+  return guarded([&] {
+    auto& r = rt(p);
+    check_mode(mode);
+    auto cache = read_cache(cache_path);
+    bool dirty = false;
+    for (int s = 0; s < (int)p->steps.size(); ++s) {
+      const StepPlan& sp = p->steps[s];
+      std::string key = tune_key(mode, sp, r.B);
+      auto it = cache.find(key);
+      std::vector<std::pair<int, int>> cands;
+      if (it != cache.end()) {
+        cands.push_back(it->second);
+      } else {
+        for (int sw = 0; sw < 2; ++sw)
+          for (int c = 0; c < gemm_config_count(); ++c)
+            if (sw ? gemm_config_fits(c, sp.n, sp.k, sp.m) : gemm_config_fits(c, sp.m, sp.k, sp.n))
+              cands.push_back({c, sw});
+        // the generic kernel only competes on small steps (or when no tile fits)
+        if (cands.empty() || sp.m + sp.k + sp.n <= 22)
+          for (int tk : {1, 8, 64})
+            if (tk == 1 || (1 << sp.k) >= tk) cands.push_back({-1 - tk, 0});
+      }
+      float best = 1e30f;
+      std::pair<int, int> pick = cands[0];
+      for (auto& c : cands) {
+        r.cfg[s] = c.first >= 0 ? c.first : -1;
+        r.swap[s] = (char)c.second;
+        if (c.first < 0) r.tk[s] = -1 - c.first;
+        if (cands.size() == 1) break;
+        float once = time_step(p, s, 1);
+        if (once > 3.0f * best) continue;  // clearly slower: no repeats
+        float ms = std::min(once, time_step(p, s, 2));
+        if (ms < best) {
+          best = ms;
+          pick = c;
+        }
+      }
+      r.cfg[s] = pick.first >= 0 ? pick.first : -1;
+      r.swap[s] = (char)pick.second;
+      if (pick.first < 0) r.tk[s] = -1 - pick.first;
+      if (it == cache.end()) {
+        cache[key] = pick;
+        dirty = true;
+      }
+    }
+    if (dirty) write_cache(cache_path, cache);
+    drop_graphs(p);
+    HIPCHECK(hipStreamSynchronize(r.st));
+  });
+}
+
+extern "C" ltn_status ltn_profile_steps(ltn_plan* p, uint64_t first, int32_t mode, float* ms_out) {
+  return guarded([&] {
+    auto& r = rt(p);
+    check_mode(mode);
+    require(ms_out != nullptr, "ms_out is NULL");
+    set_ids(p, nullptr, first, r.B, true);
+    const GatherDesc* gd = reinterpret_cast<const GatherDesc*>(r.ws + r.lay.gd_fwd);
+    launch_gather(gd, (int)p->leaves.size(), r.max_leaf_elems,
+                  reinterpret_cast<const float2*>(r.ws + r.lay.leafdata), arena_ptr(p, 0),
+                  reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids), r.B, r.st);
+    std::vector<hipEvent_t> ev(p->steps.size() + 1);
+    for (auto& e : ev) HIPCHECK(hipEventCreate(&e));
+    HIPCHECK(hipEventRecord(ev[0], r.st));
+    for (int s = 0; s < (int)p->steps.size(); ++s) {
+      enqueue_step(p, s, r.B, false);
+      HIPCHECK(hipEventRecord(ev[s + 1], r.st));
+    }
+    HIPCHECK(hipEventSynchronize(ev.back()));
+    for (int s = 0; s < (int)p->steps.size(); ++s) HIPCHECK(hipEventElapsedTime(&ms_out[s], ev[s], ev[s + 1]));
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    check_launch();
+  });
+}
+
+extern "C" ltn_status ltn_step_kernel(const ltn_plan* p, int32_t step, int32_t* cfg, int32_t* swap,
+                                      int32_t* tk) {
+  return guarded([&] {
+    require(p && p->rt, "plan is not bound");
+    require(step >= 0 && step < (int32_t)p->steps.size(), "step out of range");
+    if (cfg) *cfg = p->rt->cfg[step];
+    if (swap) *swap = p->rt->swap[step];
+    if (tk) *tk = p->rt->tk[step];
+  });
+}

@@ -1,0 +1,70 @@
+"""GPU adjoint contraction (torch.autograd.Function over libltn) against
+the oracle's gradient references."""
+import os
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import banner, rel_l2
+from workload import make_workload, make_rqc, sample_bitstrings, Workload
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def _run(torch, w, batch=0):
+    import paper_2205_00393_amd as P
+    from paper_2205_00393_amd.autograd import Amplitudes
+    pr = P.prepare(w, alphas=(0.5, 1.0), taus=(0.0, 0.3), n_seeds=3)
+    plan = pr.plan()
+    plan.bind(batch=batch, grad=True, budget_bytes=8 << 30)
+    ids = [pr.slice_of_bitstring(int(x)) for x in w.bitstrings]
+    angles = torch.tensor(w.circuit.angles(), dtype=torch.float64, device="cuda",
+                          requires_grad=True)
+    out = Amplitudes.apply(angles, plan, ids)
+    psi = out[torch.as_tensor(np.asarray(w.bitstrings), device="cuda")]
+    loss = torch.sum(torch.log(torch.abs(psi) ** 2))
+    loss.backward()
+    torch.cuda.synchronize()
+    return psi.detach().cpu().numpy(), float(loss), angles.grad.cpu().numpy()
+
+
+def _small_workload():
+    c = make_rqc(3, 3, 6, u3_seed=7)
+    bs = sample_bitstrings(9, 32, 1)
+    return Workload("u3_9", c, tuple(range(9)), {}, None, True, bs)
+
+
+def test_small_gradient_against_sv_adjoint(torch):
+    from oracle import gradients as gr
+    w = _small_workload()
+    banner("u3 3x3 gradient")
+    psi, loss, g = _run(torch, w, batch=5)
+    L, gref = gr.sv_adjoint(w.circuit, w.bitstrings)
+    from oracle import statevector as sv
+    assert rel_l2(psi, sv.bitstring_amplitudes(w.circuit, w.bitstrings)) < 1e-4
+    assert abs(loss - L) < 1e-3 * abs(L)
+    assert rel_l2(g, gref) < 1e-3
+
+
+def test_rqc20_gradient(torch):
+    path = os.path.join(GOLDEN, "rqc20_grad_reference.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden gradient reference not generated")
+    ref = np.load(path)
+    w = make_workload("rqc20_grad")
+    assert np.array_equal(ref["bitstrings"], w.bitstrings)
+    banner("rqc20 gradient")
+    psi, loss, g = _run(torch, w)
+    assert rel_l2(psi, ref["amplitudes"]) < 1e-4
+    assert rel_l2(g, ref["grad"]) < 1e-3
+    sub = ref["subset"]
+    assert rel_l2(g[sub], ref["finite_diff"]) < 1e-3
+    assert rel_l2(g[sub], ref["param_shift"]) < 1e-3
