@@ -22,6 +22,21 @@ PEAK_HBM_GBS = 8000.0
 GOLDEN = os.path.join(ROOT, "tests", "golden", "rqc30_amplitudes.npy")
 
 
+def counter_traffic(mode):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, or None when the kernel source has changed
+    since the counters were taken (or no summary exists for this mode)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_cgemm_{'c64' if mode == 'c64' else 'split'}__rqc30_{mode}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_2205_00393_amd", "csrc", "k_mfma.hip"), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -58,7 +73,19 @@ def main():
     ap.add_argument("--mode", default="c64", choices=["c64", "split_f16", "split_bf16"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe << 20
+        x = torch.ones(n, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); slices are "
               "independent, so more GPUs would each take a share of the slice range.",
@@ -134,7 +161,7 @@ def main():
     log(f"MFMA steps: {mf_launch} launches/batch, {mf_ms:.2f} of {total_ms:.2f} ms per batch, "
         f"{achieved:.2f} TFLOP/s")
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
+                "frac": round(achieved / peak, 4), "traffic": counter_traffic(args.mode),
                 "kernel": "k_cgemm_c64", "launches_per_batch": mf_launch,
                 "share_of_step_time": round(mf_ms / total_ms, 4) if total_ms else None}
 
