@@ -150,8 +150,8 @@ def main():
     nb = batch
     mf_flops, mf_ms, mf_launch = 0.0, 0.0, 0
     for k, st in enumerate(steps):
-        cfg, _, _ = plan.step_kernel(k)
-        if cfg >= 0:
+        kind, _, _, _ = plan.step_kernel(k, args.mode)
+        if kind > 0:
             mf_flops += 8.0 * (1 << (st["m"] + st["k"] + st["n"])) * nb
             mf_ms += ms[k]
             mf_launch += 1

@@ -56,11 +56,16 @@ enum {
 };
 
 /* Precision of the contraction steps (all accumulate in FP32 and sum the
- * slices in FP64). */
+ * slices in FP64). In the split modes every step that takes the MFMA GEMM
+ * with at least 8 contracted complex elements splits each real part of
+ * both operands, scaled by an exact power of two, into hi + lo in fp16
+ * (11 + 11 bits) or bf16 (8 + 8 bits) and sums hi*hi, hi*lo and lo*hi on
+ * the matrix cores; the other steps stay complex64. Tensors stay complex64
+ * in memory. */
 enum {
   LTN_C64 = 0,        /* complex64 GEMMs on FP32 MFMA / FP32 VALU          */
   LTN_SPLIT_F16 = 1,  /* each real part split into fp16 hi + lo (scaled)   */
-  LTN_SPLIT_BF16 = 2  /* each real part split into bf16 hi + lo            */
+  LTN_SPLIT_BF16 = 2  /* each real part split into bf16 hi + lo (scaled)   */
 };
 
 /* ------------------------------------------------------------------------
@@ -274,7 +279,8 @@ ltn_status ltn_execute_range(ltn_plan* plan, uint64_t begin, uint64_t end, int32
 ltn_status ltn_set_params(ltn_plan* plan, const double* d_angles);
 
 /* Gradient of a real loss with respect to the u3 angles, by an adjoint
- * contraction that recomputes every slice's intermediates. d_cotangent is
+ * contraction that recomputes every slice's intermediates (complex64 mode
+ * only; other modes return LTN_E_UNSUPPORTED). d_cotangent is
  * the loss gradient with respect to the output vector (complex128,
  * 2^n_open entries, PyTorch convention dL/dRe + i dL/dIm). Adds the
  * forward result into d_out (may be NULL) and dL/dangle into d_angle_grad
@@ -291,11 +297,13 @@ ltn_status ltn_autotune(ltn_plan* plan, int32_t mode, const char* cache_path);
  * n_steps floats of milliseconds into ms_out. Synchronises the stream. */
 ltn_status ltn_profile_steps(ltn_plan* plan, uint64_t first_slice, int32_t mode, float* ms_out);
 
-/* Kernel chosen for a step after ltn_bind / ltn_autotune: cfg = MFMA tile
- * configuration (-1: generic kernel), swap = operands exchanged on the MFMA
- * (rows from B), tk = generic kernel threads per output. */
-ltn_status ltn_step_kernel(const ltn_plan* plan, int32_t step, int32_t* cfg, int32_t* swap,
-                           int32_t* tk);
+/* Kernel chosen for a step in a mode after ltn_bind / ltn_autotune:
+ * kind 0 = generic VALU kernel (tk threads per output), 1 = complex64 MFMA
+ * GEMM, 2 = split-precision MFMA GEMM; cfg = tile configuration of that
+ * kind (-1 for the generic kernel); swap = operands exchanged on the MFMA
+ * (its rows come from B). Requires a bound plan. */
+ltn_status ltn_step_kernel(const ltn_plan* plan, int32_t step, int32_t mode, int32_t* kind,
+                           int32_t* cfg, int32_t* swap, int32_t* tk);
 
 void ltn_plan_free(ltn_plan* plan);
 const char* ltn_last_error(void);

@@ -22,9 +22,18 @@ __global__ void k_set_range(uint64_t* d, uint64_t base, int n) {
   if (i < n) d[i] = base + (uint64_t)i;
 }
 
+// wave-wide max, then one atomic per wave (non-negative floats order like
+// their bit patterns)
+__device__ __forceinline__ void record_max(uint32_t* slot, float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0 && v > 0.f) atomicMax(slot, __float_as_uint(v));
+}
+
 // one block per (leaf, slice); threads run over the leaf's elements
 __global__ void k_gather(const GatherDesc* __restrict__ desc, const float2* __restrict__ src,
-                         float2* __restrict__ arena, const uint64_t* __restrict__ ids, int nb) {
+                         float2* __restrict__ arena, const uint64_t* __restrict__ ids, int nb,
+                         uint32_t* scales, int bstride) {
   const GatherDesc& g = desc[blockIdx.x];
   int b = blockIdx.y;
   uint64_t s = ids[b];
@@ -32,11 +41,15 @@ __global__ void k_gather(const GatherDesc* __restrict__ desc, const float2* __re
   for (int i = 0; i < g.nsl; ++i) base += (int64_t)((s >> g.sl_bit[i]) & 1) << g.sl_src_bit[i];
   int64_t n = int64_t(1) << g.rank;
   float2* dst = arena + g.dst_off + (int64_t)b * n;
+  float vmax = 0.f;
   for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
     int64_t o = base;
     for (int j = 0; j < g.rank; ++j) o += ((c >> j) & 1) << g.src_bit[j];
-    dst[c] = src[o];
+    float2 v = src[o];
+    vmax = fmaxf(vmax, fmaxf(fabsf(v.x), fabsf(v.y)));
+    dst[c] = v;
   }
+  if (scales) record_max(scales + g.tensor * (int64_t)bstride + b, vmax);
 }
 
 __device__ __forceinline__ uint64_t pdep(uint64_t x, uint64_t mask) {
@@ -260,6 +273,10 @@ __global__ __launch_bounds__(256) void k_generic(GenericDesc d) {
       } else {
         *O = make_float2(re, im);
       }
+      if (d.scale_out) {
+        float v = fmaxf(fabsf(re), fabsf(im));
+        if (v > 0.f) atomicMax(d.scale_out + b, __float_as_uint(v));
+      }
     }
   }
 }
@@ -285,10 +302,11 @@ void launch_set_range(uint64_t* d_ids, uint64_t base, int n, hipStream_t st) {
 }
 
 void launch_gather(const GatherDesc* d_desc, int n_leaves, int max_elems, const float2* leafdata,
-                   float2* arena, const uint64_t* ids, int nb, hipStream_t st) {
+                   float2* arena, const uint64_t* ids, int nb, uint32_t* scales, int bstride,
+                   hipStream_t st) {
   int threads = max_elems >= 256 ? 256 : (max_elems >= 64 ? max_elems : 64);
   hipLaunchKernelGGL(k_gather, dim3(n_leaves, nb), dim3(threads), 0, st, d_desc, leafdata, arena,
-                     ids, nb);
+                     ids, nb, scales, bstride);
 }
 
 static SliceOut make_so(const int32_t* sl, const int32_t* ob, int n) {

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "ltn.h"
+
 namespace ltn {
 
 constexpr int kMaxLeafRank = 32;
@@ -14,6 +16,7 @@ constexpr int kMaxLeafRank = 32;
 // takes the value given by the slice id).
 struct GatherDesc {
   int64_t src_off;   // element offset in the leaf-data area
+  int64_t tensor;    // tensor id (slot of its per-slice max in split modes)
   int64_t dst_off;   // element offset of slice 0 in the arena
   int32_t rank;      // unsliced rank (dst has 2^rank elements per slice)
   int32_t nsl;       // number of sliced axes
@@ -41,12 +44,14 @@ struct GenericDesc {
   int32_t conjQ;
   int32_t accumulate;    // add into out instead of overwrite
   int32_t nb;            // slices
+  uint32_t* scale_out;   // if set: record the output's per-slice max |x|
 };
 
 void launch_set_ids(uint64_t* d_ids, const uint64_t* h_ids, int n, hipStream_t st);
 void launch_set_range(uint64_t* d_ids, uint64_t base, int n, hipStream_t st);
 void launch_gather(const GatherDesc* d_desc, int n_leaves, int max_elems, const float2* leafdata,
-                   float2* arena, const uint64_t* ids, int nb, hipStream_t st);
+                   float2* arena, const uint64_t* ids, int nb, uint32_t* scales, int bstride,
+                   hipStream_t st);
 void launch_reduce(const float2* root, int rank, uint64_t out_mask, const int32_t* sl_bits,
                    const int32_t* out_bits, int n_sl, const uint64_t* ids, int nb, double* out,
                    hipStream_t st);
@@ -73,13 +78,14 @@ struct GemmDesc {
   int32_t m, k, n;
   uint64_t cmask;
   int32_t nb;
-  int32_t cfg;           // tile configuration id
-  const uint32_t* scale_a; // split mode: per-slice max |x| bits of A
-  const uint32_t* scale_b;
+  int32_t cfg;             // tile configuration id (per mode)
+  const uint32_t* scale_a;   // split modes: per-slice max |x| (float bits) of A
+  const uint32_t* scale_b;   //              and of B
+  uint32_t* scale_c;         // if set: record the output's per-slice max |x|
 };
-int gemm_config_count();
-bool gemm_config_fits(int cfg, int m, int k, int n);
-const char* gemm_config_name(int cfg);
+int gemm_config_count(int mode);
+bool gemm_config_fits(int cfg, int m, int k, int n, int mode);
+const char* gemm_config_name(int cfg, int mode);
 void launch_cgemm(const GemmDesc& d, int mode, hipStream_t st);
 
 }  // namespace ltn

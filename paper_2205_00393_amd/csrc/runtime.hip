@@ -42,9 +42,12 @@ struct ltn_plan_impl {
   std::vector<GatherDesc> gd_fwd, gd_grad, gd_gcot;
   std::vector<ParamLeaf> pl;
   std::vector<int32_t> sl_bits, out_bits;
-  std::vector<int> cfg;  // per step: gemm config or -1
-  std::vector<int> tk;   // per step: generic threads per output
-  std::vector<char> swap;
+  // kernel choice per mode and step: kind 0 = generic (tk threads per
+  // output), 1 = complex64 MFMA GEMM, 2 = split MFMA GEMM (cfg, swap)
+  struct Choice {
+    int kind = 0, cfg = -1, swap = 0, tk = 1;
+  };
+  std::vector<Choice> choice[3];
   std::vector<char> needs_grad;
   hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
   hipGraph_t graph_src[3] = {nullptr, nullptr, nullptr};
@@ -94,9 +97,10 @@ float2* arena_ptr(ltn_plan* p, uint64_t off_bytes) {
   return reinterpret_cast<float2*>(r.ws + r.lay.arena + off_bytes * (uint64_t)r.B);
 }
 
-int default_cfg(int m, int k, int n) {
-  for (int c = 0; c < 8; ++c)
-    if (gemm_config_fits(c, m, k, n)) return c;
+int default_cfg(int m, int k, int n, int mode) {
+  int lim = mode == LTN_C64 ? 8 : gemm_config_count(mode);
+  for (int c = 0; c < lim; ++c)
+    if (gemm_config_fits(c, m, k, n, mode)) return c;
   return -1;
 }
 
@@ -107,7 +111,12 @@ int default_tk(int k, uint64_t outs) {
   return tk;
 }
 
-void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena) {
+uint32_t* slot(ltn_plan* p, int tensor) {
+  auto& r = *p->rt;
+  return reinterpret_cast<uint32_t*>(r.ws + r.lay.scales) + (size_t)tensor * r.B;
+}
+
+void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena, int mode) {
   auto& r = *p->rt;
   const StepPlan& sp = p->steps[s];
   const TensorPlan &ta = p->tensors[sp.a], &tb = p->tensors[sp.b], &tc = p->tensors[sp.out];
@@ -115,9 +124,11 @@ void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena) {
   float2* B = arena_ptr(p, gradarena ? tb.goff : tb.off);
   float2* C = arena_ptr(p, gradarena ? tc.goff : tc.off);
   const uint64_t cm = sp.c_mask_a, full = (sp.m + sp.n) >= 64 ? ~0ull : ((1ull << (sp.m + sp.n)) - 1);
-  if (r.cfg[s] >= 0) {
+  const auto& ch = r.choice[mode][s];
+  const bool split = mode != LTN_C64;
+  if (ch.kind > 0) {
     GemmDesc d{};
-    bool sw = r.swap[s];
+    bool sw = ch.swap;
     d.A = sw ? B : A;
     d.B = sw ? A : B;
     d.C = C;
@@ -129,8 +140,13 @@ void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena) {
     d.k = sp.k;
     d.cmask = sw ? (~cm & full) : cm;
     d.nb = nb;
-    d.cfg = r.cfg[s];
-    launch_cgemm(d, LTN_C64, r.st);
+    d.cfg = ch.cfg;
+    if (split) {
+      d.scale_a = slot(p, sw ? sp.b : sp.a);
+      d.scale_b = slot(p, sw ? sp.a : sp.b);
+      d.scale_c = slot(p, sp.out);
+    }
+    launch_cgemm(d, ch.kind == 2 ? mode : LTN_C64, r.st);
   } else {
     GenericDesc g{};
     g.P = A;
@@ -149,17 +165,23 @@ void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena) {
     g.ox = cm;
     g.oy = ~cm & full;
     g.nb = nb;
-    launch_generic(g, r.tk[s], r.st);
+    if (split) g.scale_out = slot(p, sp.out);
+    launch_generic(g, ch.tk, r.st);
   }
 }
 
-void enqueue_forward(ltn_plan* p, int nb, bool gradarena) {
+void enqueue_forward(ltn_plan* p, int nb, bool gradarena, int mode) {
   auto& r = *p->rt;
   const GatherDesc* gd = reinterpret_cast<const GatherDesc*>(r.ws + (gradarena ? r.lay.gd_grad : r.lay.gd_fwd));
+  uint32_t* scales = nullptr;
+  if (mode != LTN_C64) {
+    scales = reinterpret_cast<uint32_t*>(r.ws + r.lay.scales);
+    launch_fill_zero(scales, al((size_t)r.B * p->tensors.size() * 4), r.st);
+  }
   launch_gather(gd, (int)p->leaves.size(), r.max_leaf_elems,
                 reinterpret_cast<const float2*>(r.ws + r.lay.leafdata), arena_ptr(p, 0),
-                reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids), nb, r.st);
-  for (int s = 0; s < (int)p->steps.size(); ++s) enqueue_step(p, s, nb, gradarena);
+                reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids), nb, scales, r.B, r.st);
+  for (int s = 0; s < (int)p->steps.size(); ++s) enqueue_step(p, s, nb, gradarena, mode);
 }
 
 void enqueue_reduce(ltn_plan* p, int nb, bool gradarena, double* out) {
@@ -195,7 +217,7 @@ void run_batch(ltn_plan* p, int nb, int mode, double* out) {
       hipError_t e = hipStreamBeginCapture(r.cap, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
         try {
-          enqueue_forward(p, nb, false);
+          enqueue_forward(p, nb, false, mode);
         } catch (...) {
           r.st = bound;
           (void)hipStreamEndCapture(r.cap, &g);
@@ -210,7 +232,7 @@ void run_batch(ltn_plan* p, int nb, int mode, double* out) {
     }
     HIPCHECK(hipGraphLaunch(r.graph[mode], r.st));
   } else {
-    enqueue_forward(p, nb, false);
+    enqueue_forward(p, nb, false, mode);
   }
   enqueue_reduce(p, nb, false, out);
   check_launch();
@@ -218,7 +240,6 @@ void run_batch(ltn_plan* p, int nb, int mode, double* out) {
 
 void check_mode(int mode) {
   require(mode == LTN_C64 || mode == LTN_SPLIT_F16 || mode == LTN_SPLIT_BF16, "unknown mode");
-  if (mode != LTN_C64) fail(LTN_E_UNSUPPORTED, "split precision is not available in this build");
 }
 
 }  // namespace
@@ -289,6 +310,7 @@ extern "C" ltn_status ltn_bind(ltn_plan* p, void* d_ws, size_t bytes, int32_t gr
         g.sl_bit[j] = (int8_t)lp.sl_bit[j];
       }
       const TensorPlan& t = p->tensors[lp.tensor];
+      g.tensor = lp.tensor;
       g.dst_off = (int64_t)(t.off * (uint64_t)B / 8);
       r->gd_fwd.push_back(g);
       g.dst_off = (int64_t)(t.goff * (uint64_t)B / 8);
@@ -305,22 +327,28 @@ extern "C" ltn_status ltn_bind(ltn_plan* p, void* d_ws, size_t bytes, int32_t gr
       r->out_bits.push_back(pr.second);
     }
     require(r->sl_bits.size() <= 32, "more than 32 sliced open indices");
-    // kernel choice per step
-    for (auto& sp : p->steps) {
-      int c = -1;
-      bool sw = false;
-      if (sp.kernel == LTN_K_MFMA) {
-        sw = (sp.c_mask_a & 1) != 0;  // put the output's lowest bits on the MFMA columns
-        c = sw ? default_cfg(sp.n, sp.k, sp.m) : default_cfg(sp.m, sp.k, sp.n);
-        if (c < 0) {
-          sw = !sw;
-          c = sw ? default_cfg(sp.n, sp.k, sp.m) : default_cfg(sp.m, sp.k, sp.n);
+    // kernel choice per mode and step (refined by ltn_autotune)
+    for (int mode = 0; mode < 3; ++mode)
+      for (auto& sp : p->steps) {
+        ltn_plan_impl::Choice ch;
+        ch.tk = default_tk(sp.k, (1ull << (sp.m + sp.n)) * (uint64_t)B);
+        if (sp.kernel == LTN_K_MFMA) {
+          // MFMA columns follow the output's lowest bits when possible
+          bool nat = (sp.c_mask_a & 1) != 0;
+          for (int kind : {mode == LTN_C64 ? 1 : 2, 1}) {
+            int km = kind == 2 ? mode : LTN_C64;
+            for (bool sw : {nat, !nat}) {
+              int c = sw ? default_cfg(sp.n, sp.k, sp.m, km) : default_cfg(sp.m, sp.k, sp.n, km);
+              if (c >= 0 && ch.kind == 0) {
+                ch.kind = kind;
+                ch.cfg = c;
+                ch.swap = sw;
+              }
+            }
+          }
         }
+        r->choice[mode].push_back(ch);
       }
-      r->cfg.push_back(c);
-      r->swap.push_back(sw);
-      r->tk.push_back(default_tk(sp.k, (1ull << (sp.m + sp.n)) * (uint64_t)B));
-    }
     r->needs_grad.assign(p->tensors.size(), 0);
     for (size_t v = 0; v < p->tensors.size(); ++v) {
       if ((int)v < p->L)
@@ -402,6 +430,7 @@ extern "C" ltn_status ltn_execute_grad(ltn_plan* p, const uint64_t* ids, uint64_
   return guarded([&] {
     auto& r = rt(p);
     check_mode(mode);
+    if (mode != LTN_C64) fail(LTN_E_UNSUPPORTED, "gradients run in complex64 only");
     require(r.grad, "plan was bound without gradient workspace");
     require(d_cot && d_angle_grad, "NULL argument");
     require(n == 0 || ids, "slice_ids is NULL");
@@ -415,7 +444,7 @@ extern "C" ltn_status ltn_execute_grad(ltn_plan* p, const uint64_t* ids, uint64_
     for (uint64_t off = 0; off < n; off += (uint64_t)r.B) {
       int nb = (int)std::min<uint64_t>((uint64_t)r.B, n - off);
       set_ids(p, ids + off, 0, nb, false);
-      enqueue_forward(p, nb, true);
+      enqueue_forward(p, nb, true, LTN_C64);
       if (d_out) enqueue_reduce(p, nb, true, reinterpret_cast<double*>(d_out));
       const TensorPlan& root = p->tensors[p->root];
       launch_root_cotangent(reinterpret_cast<const double*>(d_cot), root.rank, p->out_mask,
@@ -521,14 +550,14 @@ void write_cache(const char* path, const std::map<std::string, std::pair<int, in
   f << "}\n";
 }
 
-float time_step(ltn_plan* p, int s, int reps) {
+float time_step(ltn_plan* p, int s, int reps, int mode) {
   auto& r = *p->rt;
   hipEvent_t a, b;
   HIPCHECK(hipEventCreate(&a));
   HIPCHECK(hipEventCreate(&b));
-  enqueue_step(p, s, r.B, false);  // untimed warm-up launch
+  enqueue_step(p, s, r.B, false, mode);  // untimed warm-up launch
   HIPCHECK(hipEventRecord(a, r.st));
-  for (int i = 0; i < reps; ++i) enqueue_step(p, s, r.B, false);
+  for (int i = 0; i < reps; ++i) enqueue_step(p, s, r.B, false, mode);
   HIPCHECK(hipEventRecord(b, r.st));
   HIPCHECK(hipEventSynchronize(b));
   float ms = 0;
@@ -552,56 +581,87 @@ void drop_graphs(ltn_plan* p) {
 }  // namespace
 
 // Candidates: every MFMA tile configuration that fits the step in either
-// operand role, and the generic kernel with 1, 8 or 64 threads per output.
-// Encoded as (cfg, swap) with cfg = -1 - tk for the generic kernel.
+// operand role (split tiles first in the split modes, then complex64 tiles),
+// and the generic kernel with 1, 8 or 64 threads per output on small steps.
+// Cache entries: [kind * 1000 + cfg, swap] for MFMA kinds, [-tk, 0] for the
+// generic kernel.
 extern "C" ltn_status ltn_autotune(ltn_plan* p, int32_t mode, const char* cache_path) {
   return guarded([&] {
     auto& r = rt(p);
     check_mode(mode);
     auto cache = read_cache(cache_path);
     bool dirty = false;
+    using Choice = ltn_plan_impl::Choice;
+    auto encode = [](const Choice& c) {
+      return c.kind > 0 ? std::make_pair(c.kind * 1000 + c.cfg, c.swap) : std::make_pair(-c.tk, 0);
+    };
+    auto decode = [](std::pair<int, int> e) {
+      Choice c;
+      if (e.first >= 0) {
+        c.kind = e.first / 1000;
+        c.cfg = e.first % 1000;
+        c.swap = e.second;
+      } else {
+        c.kind = 0;
+        c.tk = -e.first;
+      }
+      return c;
+    };
+    // the synchronising time_step below must not run inside a capture
+    // and a stale graph would keep the old kernels
+    drop_graphs(p);
+    if (mode != LTN_C64)
+      launch_fill_zero(r.ws + r.lay.scales, al((size_t)r.B * p->tensors.size() * 4), r.st);
     for (int s = 0; s < (int)p->steps.size(); ++s) {
       const StepPlan& sp = p->steps[s];
       std::string key = tune_key(mode, sp, r.B);
       auto it = cache.find(key);
-      std::vector<std::pair<int, int>> cands;
+      std::vector<Choice> cands;
       if (it != cache.end()) {
-        cands.push_back(it->second);
+        cands.push_back(decode(it->second));
       } else {
-        for (int sw = 0; sw < 2; ++sw)
-          for (int c = 0; c < gemm_config_count(); ++c)
-            if (sw ? gemm_config_fits(c, sp.n, sp.k, sp.m) : gemm_config_fits(c, sp.m, sp.k, sp.n))
-              cands.push_back({c, sw});
+        for (int kind : {2, 1}) {
+          if (kind == 2 && mode == LTN_C64) continue;
+          int km = kind == 2 ? mode : LTN_C64;
+          for (int sw = 0; sw < 2; ++sw)
+            for (int c = 0; c < gemm_config_count(km); ++c)
+              if (sw ? gemm_config_fits(c, sp.n, sp.k, sp.m, km) : gemm_config_fits(c, sp.m, sp.k, sp.n, km)) {
+                Choice ch;
+                ch.kind = kind;
+                ch.cfg = c;
+                ch.swap = sw;
+                cands.push_back(ch);
+              }
+        }
         // the generic kernel only competes on small steps (or when no tile fits)
         if (cands.empty() || sp.m + sp.k + sp.n <= 22)
           for (int tk : {1, 8, 64})
-            if (tk == 1 || (1 << sp.k) >= tk) cands.push_back({-1 - tk, 0});
+            if (tk == 1 || (1 << sp.k) >= tk) {
+              Choice ch;
+              ch.tk = tk;
+              cands.push_back(ch);
+            }
       }
       float best = 1e30f;
-      std::pair<int, int> pick = cands[0];
+      Choice pick = cands[0];
       for (auto& c : cands) {
-        r.cfg[s] = c.first >= 0 ? c.first : -1;
-        r.swap[s] = (char)c.second;
-        if (c.first < 0) r.tk[s] = -1 - c.first;
+        r.choice[mode][s] = c;
         if (cands.size() == 1) break;
-        float once = time_step(p, s, 1);
+        float once = time_step(p, s, 1, mode);
         if (once > 3.0f * best) continue;  // clearly slower: no repeats
-        float ms = std::min(once, time_step(p, s, 2));
+        float ms = std::min(once, time_step(p, s, 2, mode));
         if (ms < best) {
           best = ms;
           pick = c;
         }
       }
-      r.cfg[s] = pick.first >= 0 ? pick.first : -1;
-      r.swap[s] = (char)pick.second;
-      if (pick.first < 0) r.tk[s] = -1 - pick.first;
+      r.choice[mode][s] = pick;
       if (it == cache.end()) {
-        cache[key] = pick;
+        cache[key] = encode(pick);
         dirty = true;
       }
     }
     if (dirty) write_cache(cache_path, cache);
-    drop_graphs(p);
     HIPCHECK(hipStreamSynchronize(r.st));
   });
 }
@@ -613,14 +673,19 @@ extern "C" ltn_status ltn_profile_steps(ltn_plan* p, uint64_t first, int32_t mod
     require(ms_out != nullptr, "ms_out is NULL");
     set_ids(p, nullptr, first, r.B, true);
     const GatherDesc* gd = reinterpret_cast<const GatherDesc*>(r.ws + r.lay.gd_fwd);
+    uint32_t* scales = nullptr;
+    if (mode != LTN_C64) {
+      scales = reinterpret_cast<uint32_t*>(r.ws + r.lay.scales);
+      launch_fill_zero(scales, al((size_t)r.B * p->tensors.size() * 4), r.st);
+    }
     launch_gather(gd, (int)p->leaves.size(), r.max_leaf_elems,
                   reinterpret_cast<const float2*>(r.ws + r.lay.leafdata), arena_ptr(p, 0),
-                  reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids), r.B, r.st);
+                  reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids), r.B, scales, r.B, r.st);
     std::vector<hipEvent_t> ev(p->steps.size() + 1);
     for (auto& e : ev) HIPCHECK(hipEventCreate(&e));
     HIPCHECK(hipEventRecord(ev[0], r.st));
     for (int s = 0; s < (int)p->steps.size(); ++s) {
-      enqueue_step(p, s, r.B, false);
+      enqueue_step(p, s, r.B, false, mode);
       HIPCHECK(hipEventRecord(ev[s + 1], r.st));
     }
     HIPCHECK(hipEventSynchronize(ev.back()));
@@ -630,13 +695,16 @@ extern "C" ltn_status ltn_profile_steps(ltn_plan* p, uint64_t first, int32_t mod
   });
 }
 
-extern "C" ltn_status ltn_step_kernel(const ltn_plan* p, int32_t step, int32_t* cfg, int32_t* swap,
-                                      int32_t* tk) {
+extern "C" ltn_status ltn_step_kernel(const ltn_plan* p, int32_t step, int32_t mode, int32_t* kind,
+                                      int32_t* cfg, int32_t* swap, int32_t* tk) {
   return guarded([&] {
     require(p && p->rt, "plan is not bound");
     require(step >= 0 && step < (int32_t)p->steps.size(), "step out of range");
-    if (cfg) *cfg = p->rt->cfg[step];
-    if (swap) *swap = p->rt->swap[step];
-    if (tk) *tk = p->rt->tk[step];
+    check_mode(mode);
+    const auto& c = p->rt->choice[mode][step];
+    if (kind) *kind = c.kind;
+    if (cfg) *cfg = c.kind > 0 ? c.cfg : -1;
+    if (swap) *swap = c.swap;
+    if (tk) *tk = c.tk;
   });
 }

@@ -149,10 +149,12 @@ class Plan:
         L.check(L.lib().ltn_profile_steps(self._h, first, L.MODES[mode], out))
         return np.asarray(out[:n], dtype=np.float64)
 
-    def step_kernel(self, k: int):
-        cfg, sw, tk = C.c_int32(), C.c_int32(), C.c_int32()
-        L.check(L.lib().ltn_step_kernel(self._h, k, C.byref(cfg), C.byref(sw), C.byref(tk)))
-        return cfg.value, sw.value, tk.value
+    def step_kernel(self, k: int, mode: str = "c64"):
+        """(kind, cfg, swap, tk): kind 0 generic, 1 complex64 MFMA, 2 split MFMA."""
+        kind, cfg, sw, tk = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        L.check(L.lib().ltn_step_kernel(self._h, k, L.MODES[mode], C.byref(kind), C.byref(cfg),
+                                        C.byref(sw), C.byref(tk)))
+        return kind.value, cfg.value, sw.value, tk.value
 
 
 @dataclass
