@@ -70,9 +70,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", default="c64", choices=["c64", "split_f16", "split_bf16"])
+    ap.add_argument("--modes", default="c64,split_f16,split_bf16",
+                    help="comma list; the first is the headline value, the others are reported beside it")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache (JSON, keyed by mode and step shape)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -107,63 +108,84 @@ def main():
     info = plan.info()
     macs_slice = info["macs_per_slice"]
     flops_step = 8.0 * macs_slice * n_slices
+    steps = plan.steps()
     log(f"planned in {t_plan:.2f}s: |S|={len(pr.sliced)} C(B,S)=2^{costs.log2_sliced:.2f} "
         f"overhead={costs.overhead:.4f} per-slice MACs={macs_slice:.3e}")
 
     batch = plan.bind(batch=n_slices) if plan.workspace_size(n_slices) < 0.7 * torch.cuda.mem_get_info()[0] \
         else plan.bind()
     log(f"bound: batch={batch}, workspace={plan.workspace_size(batch) / 2**30:.2f} GiB")
-    t0 = time.perf_counter()
-    plan.autotune(args.mode, args.tune_cache)
-    log(f"autotuned in {time.perf_counter() - t0:.2f}s")
+    ref = np.load(GOLDEN) if os.path.exists(GOLDEN) else None
 
-    out = plan.new_output()
-    for _ in range(args.warmup):
-        out.zero_()
-        plan.execute_range(0, n_slices, out, args.mode)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out.zero_()
-        plan.execute_range(0, n_slices, out, args.mode)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_step = 1e3 * dt / args.steps
-    tflops = flops_step * args.steps / dt / 1e12
-    log(f"{args.steps} steps in {dt:.3f}s: {ms_step:.2f} ms/step, {tflops:.2f} TFLOP/s")
+    def measure(mode):
+        t0 = time.perf_counter()
+        cache = args.tune_cache  # one file for all modes (keys carry the mode)
+        plan.autotune(mode, cache)
+        log(f"[{mode}] autotuned in {time.perf_counter() - t0:.2f}s")
+        out = plan.new_output()
+        for _ in range(args.warmup):
+            out.zero_()
+            plan.execute_range(0, n_slices, out, mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out.zero_()
+            plan.execute_range(0, n_slices, out, mode)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res = {"tflops": flops_step * args.steps / dt / 1e12, "ms_per_step": 1e3 * dt / args.steps,
+               "sec_per_slice": dt / args.steps / n_slices}
+        if ref is not None:
+            got = out.cpu().numpy()
+            res["rel_l2_error"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        # the dominant kernel (the MFMA complex GEMM): live per-step HIP
+        # events on the plan's stream (a replay of one batch outside the graph)
+        ms = np.zeros(len(steps))
+        reps = 3
+        for _ in range(reps):
+            ms += plan.profile_steps(0, mode)
+        ms /= reps
+        mf_flops, mf_ms, mf_launch, split_flops = 0.0, 0.0, 0, 0.0
+        for k, st in enumerate(steps):
+            kind, _, _, _ = plan.step_kernel(k, mode)
+            if kind > 0:
+                f = 8.0 * (1 << (st["m"] + st["k"] + st["n"])) * batch
+                mf_flops += f
+                mf_ms += ms[k]
+                mf_launch += 1
+                if kind == 2:
+                    split_flops += f
+        res["mfma_ms_per_batch"] = mf_ms
+        res["step_ms_per_batch"] = float(ms.sum())
+        res["mfma_launches_per_batch"] = mf_launch
+        res["mfma_tflops"] = mf_flops / (mf_ms * 1e-3) / 1e12 if mf_ms > 0 else 0.0
+        res["split_mac_fraction"] = split_flops / (8.0 * macs_slice * batch)
+        log(f"[{mode}] {res['ms_per_step']:.2f} ms/step, {res['tflops']:.2f} TFLOP/s, "
+            f"MFMA {mf_ms:.2f} of {res['step_ms_per_batch']:.2f} ms per batch "
+            f"({res['mfma_tflops']:.2f} TFLOP/s), err {res.get('rel_l2_error')}")
+        return res
 
-    err = None
-    if os.path.exists(GOLDEN):
-        ref = np.load(GOLDEN)
-        got = out.cpu().numpy()
-        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-        log(f"relative L2 error vs the oracle's complex128 amplitudes: {err:.3e}")
-
-    # roofline of the dominant kernel (the MFMA complex GEMM), from live
-    # per-step HIP events on the plan's stream (replay outside the graph)
-    steps = plan.steps()
-    ms = np.zeros(len(steps))
-    reps = 3
-    for _ in range(reps):
-        ms += plan.profile_steps(0, args.mode)
-    ms /= reps
-    nb = batch
-    mf_flops, mf_ms, mf_launch = 0.0, 0.0, 0
-    for k, st in enumerate(steps):
-        kind, _, _, _ = plan.step_kernel(k, args.mode)
-        if kind > 0:
-            mf_flops += 8.0 * (1 << (st["m"] + st["k"] + st["n"])) * nb
-            mf_ms += ms[k]
-            mf_launch += 1
-    total_ms = float(ms.sum())
-    peak = PEAK_FP32_MFMA_TFLOPS if args.mode == "c64" else PEAK_F16_MFMA_TFLOPS
-    achieved = mf_flops / (mf_ms * 1e-3) / 1e12 if mf_ms > 0 else 0.0
-    log(f"MFMA steps: {mf_launch} launches/batch, {mf_ms:.2f} of {total_ms:.2f} ms per batch, "
-        f"{achieved:.2f} TFLOP/s")
+    results = {m: measure(m) for m in args.modes.split(",")}
+    main_mode = args.modes.split(",")[0]
+    r0 = results[main_mode]
+    tflops, ms_step, err = r0["tflops"], r0["ms_per_step"], r0.get("rel_l2_error")
+    if main_mode == "c64":
+        peak, achieved = PEAK_FP32_MFMA_TFLOPS, r0["mfma_tflops"]
+    else:
+        # split: three fp16/bf16 matrix products per real product; executed
+        # matrix flops are 3x the algorithmic count
+        peak, achieved = PEAK_F16_MFMA_TFLOPS, 3.0 * r0["mfma_tflops"]
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": counter_traffic(args.mode),
-                "kernel": "k_cgemm_c64", "launches_per_batch": mf_launch,
-                "share_of_step_time": round(mf_ms / total_ms, 4) if total_ms else None}
+                "frac": round(achieved / peak, 4), "traffic": counter_traffic(main_mode),
+                "kernel": "k_cgemm_c64" if main_mode == "c64" else "k_cgemm_split",
+                "launches_per_batch": r0["mfma_launches_per_batch"],
+                "share_of_step_time": round(r0["mfma_ms_per_batch"] / r0["step_ms_per_batch"], 4)}
+    modes = {}
+    for m, r in results.items():
+        modes[m] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
+        modes[m]["speedup_vs_c64"] = round(r["tflops"] / results["c64"]["tflops"], 4) if "c64" in results else None
+        modes[m]["meets_tolerance"] = (r.get("rel_l2_error") is not None and
+                                       r["rel_l2_error"] <= (1e-4 if m == "c64" else 5e-4))
 
     cpu = None
     if not args.no_cpu:
@@ -183,16 +205,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64" if args.mode == "c64" else ("f16x2" if args.mode == "split_f16" else "bf16x2"),
+        "dtype": {"c64": "c64", "split_f16": "f16x2", "split_bf16": "bf16x2"}[main_mode],
         "data": "synthetic",
         "config": {"workload": "rqc30: 5x6 grid, 14 cycles, 6 open qubits (64 amplitudes), "
                                "max rank 26, all slices per step",
                    "slices": n_slices, "sliced_indices": len(pr.sliced), "batch": batch,
                    "log2_C_BS": round(costs.log2_sliced, 4), "overhead": round(costs.overhead, 5),
                    "macs_per_slice": macs_slice, "flops_per_step": flops_step,
-                   "mode": args.mode},
-        "sec_per_slice": dt / args.steps / n_slices,
+                   "mode": main_mode},
+        "sec_per_slice": r0["sec_per_slice"],
         "rel_l2_error": err,
+        "modes": modes,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -15,16 +15,20 @@
 // takes the real parts of A (k and k+1 on the two half-waves), the second
 // the imaginary parts.
 //
-// Split precision (k_cgemm_split): every real part x of an operand is
-// scaled by an exact power of two sigma (from the operand's largest
-// magnitude, recorded by its producer) and split as x sigma = hi + 2^-s lo
-// with hi, lo in fp16 (s = 11) or bf16 (s = 8). With hi' = 2^s hi (exact),
-//     2^s (x sigma_x)(y sigma_y) ~ hi'_x hi_y + hi_x lo_y + lo_x hi_y
-// (lo lo dropped), so three v_mfma_f32_32x32x16_{f16,bf16} per tile feed
-// one FP32 accumulator, rescaled by 2^-s / (sigma_A sigma_B) at the end.
-// Each lane supplies 8 consecutive k' = 2 k + (re|im) values of a row of A
-// as stored, and of B in the 2x2 real form: (re, -im) pairs for output
-// real parts, (im, re) pairs for imaginary parts (sign flip / half swap).
+// Split precision. Before a split step, k_split_convert writes a copy of
+// each operand in the split layout: every group of 4 consecutive
+// complex elements (32 bytes) becomes 16 bytes of hi parts then 16 bytes of
+// lo parts, (re, im) interleaved. fp16: x sigma = hi + 2^-11 lo with sigma an
+// exact power of two from the operand's largest magnitude (recorded by its
+// producer), so hi and lo stay in fp16's normal range; bf16 shares FP32's
+// exponent range and needs no scale: x = hi + lo. k_cgemm_split then sums
+// hi*hi, hi*lo and lo*hi (lo*lo dropped) with v_mfma_f32_32x32x16_{f16,bf16}
+// into one FP32 accumulator (fp16: the hi*hi product uses hi * 2^11, exact,
+// so all three terms share the accumulator's scale) and undoes the scaling
+// in the epilogue. Each lane supplies 8 consecutive k' = 2 k + (re|im) of a
+// row of A as stored, and of B in the 2x2 real form: (re, -im) pairs for
+// output real parts, (im, re) pairs for imaginary parts (sign flip / half
+// swap of each 32-bit word).
 #include "kernels.h"
 
 namespace ltn {
@@ -215,6 +219,8 @@ __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
 }
 
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 template <bool BF>
 struct SplitType;
 template <>
@@ -227,11 +233,11 @@ template <>
 struct SplitType<true> {
   using T = __bf16;
   typedef __bf16 V8 __attribute__((ext_vector_type(8)));
-  static constexpr int S = 8;
+  static constexpr int S = 0;
 };
 
 template <bool BF>
-__device__ __forceinline__ floatx16 mfma16(uint4 a, uint4 b, floatx16 c) {
+__device__ __forceinline__ floatx16 mfma16(u32x4 a, u32x4 b, floatx16 c) {
   if constexpr (BF)
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(typename SplitType<true>::V8, a),
                                                    __builtin_bit_cast(typename SplitType<true>::V8, b),
@@ -242,44 +248,82 @@ __device__ __forceinline__ floatx16 mfma16(uint4 a, uint4 b, floatx16 c) {
                                                   c, 0, 0, 0);
 }
 
-// x -> (hi, lo) of x * sigma, and hi * 2^s
-template <bool BF>
-__device__ __forceinline__ void split1(float v, float sigma, uint16_t& hi, uint16_t& hs, uint16_t& lo) {
-  using T = typename SplitType<BF>::T;
-  constexpr float P = (float)(1 << SplitType<BF>::S);
-  float x = v * sigma;
-  T h = (T)x;
-  float hf = (float)h;
-  T l = (T)((x - hf) * P);
-  T hsv = (T)(hf * P);
-  hi = __builtin_bit_cast(uint16_t, h);
-  lo = __builtin_bit_cast(uint16_t, l);
-  hs = __builtin_bit_cast(uint16_t, hsv);
+// B operand of output real parts: (re, -im) pairs; imaginary parts: (im, re)
+// (whole-vector operations: element-wise bit casts of vector elements were
+// miscompiled by this toolchain)
+__device__ __forceinline__ u32x4 bform(u32x4 w, bool im_col) {
+  if (im_col) return (w << 16) | (w >> 16);
+  return w ^ 0x80000000u;
 }
 
-// B operand of output real parts: (re, -im) pairs; imaginary parts: (im, re)
-__device__ __forceinline__ uint4 bform(uint4 w, bool im_col) {
-  if (im_col) {
-    w.x = (w.x << 16) | (w.x >> 16);
-    w.y = (w.y << 16) | (w.y >> 16);
-    w.z = (w.z << 16) | (w.z >> 16);
-    w.w = (w.w << 16) | (w.w >> 16);
-  } else {
-    w.x ^= 0x80000000u;
-    w.y ^= 0x80000000u;
-    w.z ^= 0x80000000u;
-    w.w ^= 0x80000000u;
-  }
-  return w;
+// hi * 2^11 for eight packed fp16 values (exact: a power-of-two scaling)
+__device__ __forceinline__ u32x4 times2048(u32x4 w) {
+  typedef _Float16 H8 __attribute__((ext_vector_type(8)));
+  H8 h = __builtin_bit_cast(H8, w);
+  h = h * (_Float16)2048.0f;
+  return __builtin_bit_cast(u32x4, h);
 }
+
+template <bool BF>
+__device__ __forceinline__ uint32_t split_pair(float a, float b, float sigma, uint32_t& lo) {
+  using T = typename SplitType<BF>::T;
+  constexpr float P = (float)(1 << SplitType<BF>::S);
+  float xa = a * sigma, xb = b * sigma;
+  T ha = (T)xa, hb = (T)xb;
+  T la = (T)((xa - (float)ha) * P), lb = (T)((xb - (float)hb) * P);
+  lo = (uint32_t)__builtin_bit_cast(uint16_t, la) | ((uint32_t)__builtin_bit_cast(uint16_t, lb) << 16);
+  return (uint32_t)__builtin_bit_cast(uint16_t, ha) | ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
+}
+
+// complex64 -> split layout of one tensor for nb slices (src and dst may
+// be the same buffer).
+template <bool BF>
+__global__ __launch_bounds__(256) void k_split_convert(const float2* X, float2* Y, int64_t per_slice,
+                                                       int nb, const uint32_t* slot) {
+  const int64_t groups = per_slice / 4;
+  const int64_t total = groups * nb;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int64_t b = g / groups;
+    float sigma = BF ? 1.f : scale_of(slot[b]);
+    const float4* p = reinterpret_cast<const float4*>(X) + 2 * g;
+    float4 u = p[0], v = p[1];
+    uint4 hi, lo;
+    hi.x = split_pair<BF>(u.x, u.y, sigma, lo.x);
+    hi.y = split_pair<BF>(u.z, u.w, sigma, lo.y);
+    hi.z = split_pair<BF>(v.x, v.y, sigma, lo.z);
+    hi.w = split_pair<BF>(v.z, v.w, sigma, lo.w);
+    uint4* q = reinterpret_cast<uint4*>(Y) + 2 * g;
+    q[0] = hi;
+    q[1] = lo;
+  }
+}
+
+// Split GEMM tile: 4 waves in 2 x 2, wave tile (BM/2) rows x (BNC/2)
+// complex columns. MFMA columns are complex outputs: each lane reads its B
+// value once and forms both real-form rows of it, (re, -im) for the real
+// accumulator and (im, re) for the imaginary one.
+template <int BM, int BNC, int BKC>
+struct SplitCfg {
+  static constexpr int WM = BM / 2, TM = WM / 32;
+  static constexpr int WNC = BNC / 2, TN = WNC / 32;
+  static_assert(TM >= 1 && TN >= 1 && BKC % 8 == 0, "tile too small for the split GEMM");
+};
 
 template <int BM, int BNC, int BKC, bool BF>
 __global__ __launch_bounds__(256) void k_cgemm_split(GemmDesc d) {
-  using C = Cfg<BM, BNC, BKC>;
-  constexpr int LDK = 2 * BKC + 8;  // halves per LDS row (16-byte pad)
-  static_assert(BKC % 8 == 0, "split tiles need 8 complex k per MFMA");
-  __shared__ uint16_t Ahi[BM * LDK], Alo[BM * LDK];
-  __shared__ uint16_t Bhi[BNC * LDK], Bhs[BNC * LDK], Blo[BNC * LDK];
+  using C = SplitCfg<BM, BNC, BKC>;
+  constexpr int LDK = 2 * BKC + 8;          // halves per LDS row (16-byte pad)
+  constexpr int GPR = BKC / 4;              // 4-complex groups per tile row
+  constexpr int CHA = BM * GPR * 2;         // 16-byte chunks (hi and lo)
+  constexpr int CHB = BNC * GPR * 2;
+  constexpr int RA = (CHA + 255) / 256, RB = (CHB + 255) / 256;
+  __shared__ u32x4 Ahi4[BM * LDK / 8], Alo4[BM * LDK / 8];
+  __shared__ u32x4 Bhi4[BNC * LDK / 8], Blo4[BNC * LDK / 8];
+  uint16_t* Ahi = reinterpret_cast<uint16_t*>(Ahi4);
+  uint16_t* Alo = reinterpret_cast<uint16_t*>(Alo4);
+  uint16_t* Bhi = reinterpret_cast<uint16_t*>(Bhi4);
+  uint16_t* Blo = reinterpret_cast<uint16_t*>(Blo4);
 
   const int64_t M = int64_t(1) << d.m, N = int64_t(1) << d.n, K = int64_t(1) << d.k;
   const int tiles_n = (int)(N / BNC);
@@ -291,80 +335,75 @@ __global__ __launch_bounds__(256) void k_cgemm_split(GemmDesc d) {
   const int64_t t = logical % tiles;
   const int64_t bm = t / tiles_n, bn = t % tiles_n;
 
-  const float sa = scale_of(d.scale_a[b]), sb = scale_of(d.scale_b[b]);
-  const float2* A = d.A + b * d.sA + bm * BM * K;
-  const float2* B = d.B + b * d.sB + bn * BNC * K;
-  float* Cf = reinterpret_cast<float*>(d.C + b * d.sC);
+  const float sa = BF ? 1.f : scale_of(d.scale_a[b]), sb = BF ? 1.f : scale_of(d.scale_b[b]);
+  // operands in split layout: a row of K complex is K / 4 groups of 32 bytes
+  const u32x4* A = reinterpret_cast<const u32x4*>(d.A + b * d.sA + bm * BM * K);
+  const u32x4* B = reinterpret_cast<const u32x4*>(d.B + b * d.sB + bn * BNC * K);
+  float2* Cc = d.C + b * d.sC;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int h = lane >> 5, i = lane & 31;
 
-  floatx16 acc[C::TM][C::TN];
+  floatx16 are[C::TM][C::TN], aim[C::TM][C::TN];
 #pragma unroll
   for (int x = 0; x < C::TM; ++x)
 #pragma unroll
     for (int y = 0; y < C::TN; ++y)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[x][y][v] = 0.f;
+      for (int v = 0; v < 16; ++v) {
+        are[x][y][v] = 0.f;
+        aim[x][y][v] = 0.f;
+      }
 
-  float4 ra[C::RA], rb[C::RB];
+  u32x4 ra[RA], rb[RB];
   auto load = [&](int64_t k0) {
 #pragma unroll
-    for (int r = 0; r < C::RA; ++r) {
+    for (int r = 0; r < RA; ++r) {
       int c = tid + 256 * r;
-      if (c < C::CHA) {
-        int row = c / (BKC / 2), col = c % (BKC / 2);
-        ra[r] = *reinterpret_cast<const float4*>(A + row * K + k0 + 2 * col);
+      if (c < CHA) {
+        int row = c / (2 * GPR), gp = c % (2 * GPR);
+        ra[r] = A[(row * K + k0) / 2 + gp];
       }
     }
 #pragma unroll
-    for (int r = 0; r < C::RB; ++r) {
+    for (int r = 0; r < RB; ++r) {
       int c = tid + 256 * r;
-      if (c < C::CHB) {
-        int row = c / (BKC / 2), col = c % (BKC / 2);
-        rb[r] = *reinterpret_cast<const float4*>(B + row * K + k0 + 2 * col);
+      if (c < CHB) {
+        int row = c / (2 * GPR), gp = c % (2 * GPR);
+        rb[r] = B[(row * K + k0) / 2 + gp];
       }
     }
   };
-  auto pack2 = [](uint16_t a, uint16_t b2) { return (uint32_t)a | ((uint32_t)b2 << 16); };
   auto stash = [&]() {
 #pragma unroll
-    for (int r = 0; r < C::RA; ++r) {
+    for (int r = 0; r < RA; ++r) {
       int c = tid + 256 * r;
-      if (c < C::CHA) {
-        int row = c / (BKC / 2), col = c % (BKC / 2);
-        uint16_t h0, h1, h2, h3, s0, s1, s2, s3, l0, l1, l2, l3;
-        split1<BF>(ra[r].x, sa, h0, s0, l0);
-        split1<BF>(ra[r].y, sa, h1, s1, l1);
-        split1<BF>(ra[r].z, sa, h2, s2, l2);
-        split1<BF>(ra[r].w, sa, h3, s3, l3);
-        int o = row * LDK + 4 * col;
-        *reinterpret_cast<uint2*>(&Ahi[o]) = make_uint2(pack2(h0, h1), pack2(h2, h3));
-        *reinterpret_cast<uint2*>(&Alo[o]) = make_uint2(pack2(l0, l1), pack2(l2, l3));
+      if (c < CHA) {
+        int row = c / (2 * GPR), gp = c % (2 * GPR);
+        int o = row * LDK + 8 * (gp >> 1);
+        if (gp & 1)
+          *reinterpret_cast<u32x4*>(&Alo[o]) = ra[r];
+        else
+          *reinterpret_cast<u32x4*>(&Ahi[o]) = ra[r];
       }
     }
 #pragma unroll
-    for (int r = 0; r < C::RB; ++r) {
+    for (int r = 0; r < RB; ++r) {
       int c = tid + 256 * r;
-      if (c < C::CHB) {
-        int row = c / (BKC / 2), col = c % (BKC / 2);
-        uint16_t h0, h1, h2, h3, s0, s1, s2, s3, l0, l1, l2, l3;
-        split1<BF>(rb[r].x, sb, h0, s0, l0);
-        split1<BF>(rb[r].y, sb, h1, s1, l1);
-        split1<BF>(rb[r].z, sb, h2, s2, l2);
-        split1<BF>(rb[r].w, sb, h3, s3, l3);
-        int o = row * LDK + 4 * col;
-        *reinterpret_cast<uint2*>(&Bhi[o]) = make_uint2(pack2(h0, h1), pack2(h2, h3));
-        *reinterpret_cast<uint2*>(&Bhs[o]) = make_uint2(pack2(s0, s1), pack2(s2, s3));
-        *reinterpret_cast<uint2*>(&Blo[o]) = make_uint2(pack2(l0, l1), pack2(l2, l3));
+      if (c < CHB) {
+        int row = c / (2 * GPR), gp = c % (2 * GPR);
+        int o = row * LDK + 8 * (gp >> 1);
+        if (gp & 1)
+          *reinterpret_cast<u32x4*>(&Blo[o]) = rb[r];
+        else
+          *reinterpret_cast<u32x4*>(&Bhi[o]) = rb[r];
       }
     }
   };
 
   const int arow0 = wm * C::WM + i;
-  const int bcol0 = wn * C::WNC + (i >> 1);
-  const bool im_col = (i & 1) != 0;
+  const int bcol0 = wn * C::WNC + i;
 
   load(0);
   for (int64_t k0 = 0; k0 < K; k0 += BKC) {
@@ -375,30 +414,36 @@ __global__ __launch_bounds__(256) void k_cgemm_split(GemmDesc d) {
 #pragma unroll
     for (int ch = 0; ch < BKC / 8; ++ch) {
       const int ko = 16 * ch + 8 * h;  // halves offset of this lane's 8 k'
-      uint4 ah[C::TM], al[C::TM];
+      u32x4 ah[C::TM], al[C::TM];
 #pragma unroll
       for (int x = 0; x < C::TM; ++x) {
         int o = (arow0 + 32 * x) * LDK + ko;
-        ah[x] = *reinterpret_cast<const uint4*>(&Ahi[o]);
-        al[x] = *reinterpret_cast<const uint4*>(&Alo[o]);
+        ah[x] = *reinterpret_cast<const u32x4*>(&Ahi[o]);
+        al[x] = *reinterpret_cast<const u32x4*>(&Alo[o]);
       }
 #pragma unroll
       for (int y = 0; y < C::TN; ++y) {
-        int o = (bcol0 + 16 * y) * LDK + ko;
-        uint4 bh = bform(*reinterpret_cast<const uint4*>(&Bhi[o]), im_col);
-        uint4 bs = bform(*reinterpret_cast<const uint4*>(&Bhs[o]), im_col);
-        uint4 bl = bform(*reinterpret_cast<const uint4*>(&Blo[o]), im_col);
+        int o = (bcol0 + 32 * y) * LDK + ko;
+        u32x4 bh = *reinterpret_cast<const u32x4*>(&Bhi[o]);
+        u32x4 bl = *reinterpret_cast<const u32x4*>(&Blo[o]);
+        u32x4 bs = BF ? bh : times2048(bh);
+        u32x4 rh = bform(bh, false), ih = bform(bh, true);
+        u32x4 rl = bform(bl, false), il = bform(bl, true);
+        u32x4 rs = BF ? rh : bform(bs, false), is = BF ? ih : bform(bs, true);
 #pragma unroll
         for (int x = 0; x < C::TM; ++x) {
-          acc[x][y] = mfma16<BF>(ah[x], bs, acc[x][y]);
-          acc[x][y] = mfma16<BF>(ah[x], bl, acc[x][y]);
-          acc[x][y] = mfma16<BF>(al[x], bh, acc[x][y]);
+          are[x][y] = mfma16<BF>(ah[x], rs, are[x][y]);
+          are[x][y] = mfma16<BF>(ah[x], rl, are[x][y]);
+          are[x][y] = mfma16<BF>(al[x], rh, are[x][y]);
+          aim[x][y] = mfma16<BF>(ah[x], is, aim[x][y]);
+          aim[x][y] = mfma16<BF>(ah[x], il, aim[x][y]);
+          aim[x][y] = mfma16<BF>(al[x], ih, aim[x][y]);
         }
       }
     }
   }
 
-  const float post = (1.0f / (float)(1 << SplitType<BF>::S)) / sa / sb;
+  const float post = BF ? 1.f : (1.0f / 2048.0f) / sa / sb;
   const uint64_t maskA = d.cmask;
   const uint64_t maskB = ~d.cmask & ((1ull << (d.m + d.n)) - 1);
   const uint64_t row_base = (uint64_t)(bm * BM + wm * C::WM + 4 * h);
@@ -413,8 +458,7 @@ __global__ __launch_bounds__(256) void k_cgemm_split(GemmDesc d) {
   float vmax = 0.f;
 #pragma unroll
   for (int y = 0; y < C::TN; ++y) {
-    uint64_t ncol = (uint64_t)(bn * BNC + bcol0 + 16 * y);
-    uint64_t pn = pdep64(ncol, maskB);
+    uint64_t pn = pdep64((uint64_t)(bn * BNC + bcol0 + 32 * y), maskB);
 #pragma unroll
     for (int x = 0; x < C::TM; ++x)
 #pragma unroll
@@ -422,9 +466,9 @@ __global__ __launch_bounds__(256) void k_cgemm_split(GemmDesc d) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           uint64_t addr = pbase | pt[x] | pg[g] | pq[q] | pn;
-          float v = acc[x][y][4 * g + q] * post;
-          vmax = fmaxf(vmax, fabsf(v));
-          Cf[2 * addr + (im_col ? 1 : 0)] = v;
+          float vr = are[x][y][4 * g + q] * post, vi = aim[x][y][4 * g + q] * post;
+          vmax = fmaxf(vmax, fmaxf(fabsf(vr), fabsf(vi)));
+          Cc[addr] = make_float2(vr, vi);
         }
   }
   if (d.scale_c) record_max(d.scale_c + b, vmax);
@@ -442,9 +486,9 @@ const CfgInfo kCfgs[] = {
 };
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 const CfgInfo kSplitCfgs[] = {
-    {256, 64, 16, "split_256x64x16"}, {128, 64, 16, "split_128x64x16"}, {128, 128, 16, "split_128x128x16"},
-    {128, 32, 16, "split_128x32x16"}, {64, 64, 16, "split_64x64x16"},   {64, 32, 16, "split_64x32x16"},
-    {128, 64, 8, "split_128x64x8"},   {64, 32, 8, "split_64x32x8"},
+    {128, 128, 16, "split_128x128x16"}, {128, 64, 16, "split_128x64x16"}, {64, 128, 16, "split_64x128x16"},
+    {64, 64, 16, "split_64x64x16"},     {128, 128, 8, "split_128x128x8"}, {128, 64, 8, "split_128x64x8"},
+    {64, 64, 8, "split_64x64x8"},       {256, 64, 16, "split_256x64x16"},
 };
 constexpr int kNumSplit = sizeof(kSplitCfgs) / sizeof(kSplitCfgs[0]);
 
@@ -479,18 +523,32 @@ const char* gemm_config_name(int cfg, int mode) {
   return cfg >= 0 && cfg < gemm_config_count(mode) ? info_of(cfg, mode).name : "?";
 }
 
+void launch_split_convert(const float2* X, float2* Y, int rank, int nb, const uint32_t* slot,
+                          int mode, hipStream_t st) {
+  int64_t per = int64_t(1) << rank;
+  int64_t groups = per / 4 * nb;
+  int64_t blocks = (groups + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (mode == LTN_SPLIT_BF16)
+    hipLaunchKernelGGL(k_split_convert<true>, dim3((unsigned)blocks), dim3(256), 0, st, X, Y, per, nb,
+                       slot);
+  else
+    hipLaunchKernelGGL(k_split_convert<false>, dim3((unsigned)blocks), dim3(256), 0, st, X, Y, per, nb,
+                       slot);
+}
+
 void launch_cgemm(const GemmDesc& d, int mode, hipStream_t st) {
   if (mode != LTN_C64) {
     bool bf = mode == LTN_SPLIT_BF16;
     switch (d.cfg) {
-      case 0: run_split<256, 64, 16>(d, bf, st); break;
+      case 0: run_split<128, 128, 16>(d, bf, st); break;
       case 1: run_split<128, 64, 16>(d, bf, st); break;
-      case 2: run_split<128, 128, 16>(d, bf, st); break;
-      case 3: run_split<128, 32, 16>(d, bf, st); break;
-      case 4: run_split<64, 64, 16>(d, bf, st); break;
-      case 5: run_split<64, 32, 16>(d, bf, st); break;
-      case 6: run_split<128, 64, 8>(d, bf, st); break;
-      case 7: run_split<64, 32, 8>(d, bf, st); break;
+      case 2: run_split<64, 128, 16>(d, bf, st); break;
+      case 3: run_split<64, 64, 16>(d, bf, st); break;
+      case 4: run_split<128, 128, 8>(d, bf, st); break;
+      case 5: run_split<128, 64, 8>(d, bf, st); break;
+      case 6: run_split<64, 64, 8>(d, bf, st); break;
+      case 7: run_split<256, 64, 16>(d, bf, st); break;
     }
     return;
   }

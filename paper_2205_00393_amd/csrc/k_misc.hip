@@ -238,6 +238,10 @@ __global__ __launch_bounds__(256) void k_generic(GenericDesc d) {
   const uint64_t zc = 1ull << d.zb;
   const uint64_t zstep = pdep((uint64_t)TK, d.pz), zstepq = pdep((uint64_t)TK, d.qz);
   const uint64_t z0p = pdep((uint64_t)lane, d.pz), z0q = pdep((uint64_t)lane, d.qz);
+  // running max of the outputs this lane wrote, per slice (flushed with an
+  // atomic when the slice changes and once after the loop)
+  uint64_t bcur = ~0ull;
+  float vcur = 0.f;
   for (uint64_t g = (uint64_t)blockIdx.x * per_block + threadIdx.x / TK; g < total;
        g += (uint64_t)gridDim.x * per_block) {
     uint64_t b = g >> (d.xb + d.yb);
@@ -273,10 +277,27 @@ __global__ __launch_bounds__(256) void k_generic(GenericDesc d) {
       } else {
         *O = make_float2(re, im);
       }
-      if (d.scale_out) {
-        float v = fmaxf(fabsf(re), fabsf(im));
-        if (v > 0.f) atomicMax(d.scale_out + b, __float_as_uint(v));
+    }
+    if (d.scale_out && lane == 0) {
+      if (b != bcur) {
+        if (bcur != ~0ull && vcur > 0.f) atomicMax(d.scale_out + bcur, __float_as_uint(vcur));
+        bcur = b;
+        vcur = 0.f;
       }
+      vcur = fmaxf(vcur, fmaxf(fabsf(re), fabsf(im)));
+    }
+  }
+  if (d.scale_out) {
+    // every lane is active again here: one atomic per wave if all lanes that
+    // hold a value share one slice, else one per lane
+    uint64_t b0 = __shfl(bcur, 0, 64);
+    bool same = __all(bcur == b0 || bcur == ~0ull);
+    if (same && b0 != ~0ull) {
+      float v = vcur;
+      for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+      if ((threadIdx.x & 63) == 0 && v > 0.f) atomicMax(d.scale_out + b0, __float_as_uint(v));
+    } else if (!same && bcur != ~0ull && vcur > 0.f) {
+      atomicMax(d.scale_out + bcur, __float_as_uint(vcur));
     }
   }
 }

@@ -87,5 +87,9 @@ int gemm_config_count(int mode);
 bool gemm_config_fits(int cfg, int m, int k, int n, int mode);
 const char* gemm_config_name(int cfg, int mode);
 void launch_cgemm(const GemmDesc& d, int mode, hipStream_t st);
+// complex64 tensor X (2^rank per slice, rank >= 2) -> its split-layout
+// copy Y in the given split mode (fp16 scaled by the per-slice max slot[b]).
+void launch_split_convert(const float2* X, float2* Y, int rank, int nb, const uint32_t* slot,
+                          int mode, hipStream_t st);
 
 }  // namespace ltn

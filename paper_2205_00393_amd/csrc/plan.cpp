@@ -212,6 +212,12 @@ extern "C" ltn_status ltn_plan_load(const ltn_network* net, const int32_t* path_
       }
       p->arena = align_up(high, kAlign);
     }
+    // split-precision steps read operand copies in the split layout
+    for (auto& sp : p->steps)
+      if (sp.kernel == LTN_K_MFMA && sp.k >= 3)
+        p->split_scratch = std::max<uint64_t>(
+            p->split_scratch, align_up(p->tensors[sp.a].bytes(), kAlign) + p->tensors[sp.b].bytes());
+    p->split_scratch = align_up(p->split_scratch, kAlign);
     // grad arena: every tensor and its cotangent kept
     {
       uint64_t off = 0;

@@ -68,6 +68,7 @@ struct ltn_plan {
   std::vector<std::pair<int32_t, int32_t>> out_sliced;  // (slice bit, output bit)
   int32_t n_open = 0;
   uint64_t arena = 0, garena = 0;    // per-slice bytes
+  uint64_t split_scratch = 0;        // per-slice bytes for split-layout operand copies
   ltn::BigSum macs;
   double macs_d = 0;
   ltn_options opt{};

@@ -26,7 +26,7 @@ using namespace ltn;
   } while (0)
 
 struct Layout {
-  size_t leafdata, gd_fwd, gd_grad, gd_gcot, pl, angles, leafgrad, ids, scales, arena, total;
+  size_t leafdata, gd_fwd, gd_grad, gd_gcot, pl, angles, leafgrad, ids, scales, arena, split, total;
 };
 
 struct ltn_plan_impl {
@@ -83,6 +83,8 @@ Layout layout(const ltn_plan* p, int B, int grad) {
   o = al(o + (size_t)B * p->tensors.size() * 4);
   l.arena = o;
   o = al(o + (size_t)B * (grad ? p->garena : p->arena));
+  l.split = o;
+  o = al(o + (size_t)B * p->split_scratch);
   l.total = o;
   return l;
 }
@@ -141,10 +143,20 @@ void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena, int mode) {
     d.cmask = sw ? (~cm & full) : cm;
     d.nb = nb;
     d.cfg = ch.cfg;
-    if (split) {
-      d.scale_a = slot(p, sw ? sp.b : sp.a);
-      d.scale_b = slot(p, sw ? sp.a : sp.b);
-      d.scale_c = slot(p, sp.out);
+    const bool f16 = mode == LTN_SPLIT_F16;
+    if (f16) d.scale_c = slot(p, sp.out);
+    if (ch.kind == 2) {
+      // split-layout copies of both operands in the per-batch scratch area
+      float2* As = reinterpret_cast<float2*>(r.ws + r.lay.split);
+      float2* Bs = As + (((ta.bytes() + 255) / 256 * 256) / 8) * (uint64_t)r.B;
+      launch_split_convert(A, As, ta.rank, nb, f16 ? slot(p, sp.a) : nullptr, mode, r.st);
+      launch_split_convert(B, Bs, tb.rank, nb, f16 ? slot(p, sp.b) : nullptr, mode, r.st);
+      d.A = sw ? Bs : As;
+      d.B = sw ? As : Bs;
+      if (f16) {
+        d.scale_a = slot(p, sw ? sp.b : sp.a);
+        d.scale_b = slot(p, sw ? sp.a : sp.b);
+      }
     }
     launch_cgemm(d, ch.kind == 2 ? mode : LTN_C64, r.st);
   } else {
@@ -165,7 +177,7 @@ void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena, int mode) {
     g.ox = cm;
     g.oy = ~cm & full;
     g.nb = nb;
-    if (split) g.scale_out = slot(p, sp.out);
+    if (mode == LTN_SPLIT_F16) g.scale_out = slot(p, sp.out);
     launch_generic(g, ch.tk, r.st);
   }
 }
@@ -174,7 +186,7 @@ void enqueue_forward(ltn_plan* p, int nb, bool gradarena, int mode) {
   auto& r = *p->rt;
   const GatherDesc* gd = reinterpret_cast<const GatherDesc*>(r.ws + (gradarena ? r.lay.gd_grad : r.lay.gd_fwd));
   uint32_t* scales = nullptr;
-  if (mode != LTN_C64) {
+  if (mode == LTN_SPLIT_F16) {
     scales = reinterpret_cast<uint32_t*>(r.ws + r.lay.scales);
     launch_fill_zero(scales, al((size_t)r.B * p->tensors.size() * 4), r.st);
   }
@@ -610,8 +622,11 @@ extern "C" ltn_status ltn_autotune(ltn_plan* p, int32_t mode, const char* cache_
     // the synchronising time_step below must not run inside a capture
     // and a stale graph would keep the old kernels
     drop_graphs(p);
-    if (mode != LTN_C64)
-      launch_fill_zero(r.ws + r.lay.scales, al((size_t)r.B * p->tensors.size() * 4), r.st);
+    // time on realistic values (power and clocks depend on the data): one
+    // forward pass over slices 0.. fills every tensor of the arena, and in
+    // split-fp16 mode the per-slice maxima
+    set_ids(p, nullptr, 0, r.B, true);
+    enqueue_forward(p, r.B, false, mode == LTN_C64 ? LTN_C64 : mode);
     for (int s = 0; s < (int)p->steps.size(); ++s) {
       const StepPlan& sp = p->steps[s];
       std::string key = tune_key(mode, sp, r.B);
@@ -674,7 +689,7 @@ extern "C" ltn_status ltn_profile_steps(ltn_plan* p, uint64_t first, int32_t mod
     set_ids(p, nullptr, first, r.B, true);
     const GatherDesc* gd = reinterpret_cast<const GatherDesc*>(r.ws + r.lay.gd_fwd);
     uint32_t* scales = nullptr;
-    if (mode != LTN_C64) {
+    if (mode == LTN_SPLIT_F16) {
       scales = reinterpret_cast<uint32_t*>(r.ws + r.lay.scales);
       launch_fill_zero(scales, al((size_t)r.B * p->tensors.size() * 4), r.st);
     }
