@@ -66,6 +66,23 @@ __device__ __forceinline__ float scale_of(uint32_t maxbits) {
   return __uint_as_float((uint32_t)se << 23);
 }
 
+// Block -> (slice, row tile, column tile). Hardware dispatch sends block w to
+// XCD w % 8, so each XCD first gets a contiguous 1/8 of the logical tiles;
+// inside a slice, tiles go in groups of G = 8 row tiles, column-major within a
+// group, so the blocks resident at once share both row and column panels in
+// their XCD's L2 (operand re-reads ~ A / G_n + B / G_m instead of B per row).
+__device__ __forceinline__ void tile_of(int64_t w, int64_t tiles_m, int64_t tiles_n, int nb,
+                                        int64_t& b, int64_t& bm, int64_t& bn) {
+  const int64_t tiles = tiles_m * tiles_n, total = tiles * nb;
+  const int64_t logical = (total % 8 == 0) ? (w % 8) * (total / 8) + w / 8 : w;
+  b = logical / tiles;
+  const int64_t t = logical % tiles;
+  const int64_t G = tiles_m < 8 ? tiles_m : 8;
+  const int64_t grp = t / (G * tiles_n), r = t % (G * tiles_n);
+  bm = grp * G + r % G;
+  bn = r / G;
+}
+
 template <int BM, int BNC, int BKC>
 struct Cfg {
   static constexpr int WM = BM / 2;          // rows per wave
@@ -87,16 +104,8 @@ __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
   __shared__ float2 Bs[BNC * C::LDA];
 
   const int64_t M = int64_t(1) << d.m, N = int64_t(1) << d.n, K = int64_t(1) << d.k;
-  const int tiles_n = (int)(N / BNC);
-  const int64_t tiles = (M / BM) * tiles_n;
-  const int64_t total = tiles * d.nb;
-  // XCD-aware order: consecutive logical tiles (sharing an A panel) land on
-  // the same XCD, whose L2 then serves the panel to all of them
-  int64_t w = blockIdx.x;
-  int64_t logical = (total % 8 == 0) ? (w % 8) * (total / 8) + w / 8 : w;
-  const int64_t b = logical / tiles;
-  const int64_t t = logical % tiles;
-  const int64_t bm = t / tiles_n, bn = t % tiles_n;
+  int64_t b, bm, bn;
+  tile_of(blockIdx.x, M / BM, N / BNC, d.nb, b, bm, bn);
 
   const float2* A = d.A + b * d.sA + bm * BM * K;
   const float2* B = d.B + b * d.sB + bn * BNC * K;
@@ -313,27 +322,23 @@ struct SplitCfg {
 template <int BM, int BNC, int BKC, bool BF>
 __global__ __launch_bounds__(256) void k_cgemm_split(GemmDesc d) {
   using C = SplitCfg<BM, BNC, BKC>;
-  constexpr int LDK = 2 * BKC + 8;          // halves per LDS row (16-byte pad)
-  constexpr int GPR = BKC / 4;              // 4-complex groups per tile row
-  constexpr int CHA = BM * GPR * 2;         // 16-byte chunks (hi and lo)
-  constexpr int CHB = BNC * GPR * 2;
+  // LDS rows of U 16-byte units (one unit = 4 complex of hi or lo parts);
+  // row r starts at unit U r + r / (16 / U), so that 16 consecutive rows at
+  // one group (a read pass) and the 16 / U rows x U groups of a store pass
+  // each fall on 16 distinct units, i.e. on all 64 banks once
+  constexpr int U = BKC / 4;
+  constexpr int RPP = 16 / U;               // rows per 16-chunk store pass
+  constexpr int CHA = BM * U * 2;           // 16-byte chunks (hi and lo)
+  constexpr int CHB = BNC * U * 2;
   constexpr int RA = (CHA + 255) / 256, RB = (CHB + 255) / 256;
-  __shared__ u32x4 Ahi4[BM * LDK / 8], Alo4[BM * LDK / 8];
-  __shared__ u32x4 Bhi4[BNC * LDK / 8], Blo4[BNC * LDK / 8];
-  uint16_t* Ahi = reinterpret_cast<uint16_t*>(Ahi4);
-  uint16_t* Alo = reinterpret_cast<uint16_t*>(Alo4);
-  uint16_t* Bhi = reinterpret_cast<uint16_t*>(Bhi4);
-  uint16_t* Blo = reinterpret_cast<uint16_t*>(Blo4);
+  static_assert(BM % RPP == 0 && BNC % RPP == 0, "tile rows must fill store passes");
+  __shared__ u32x4 Ahi[BM * U + BM / RPP], Alo[BM * U + BM / RPP];
+  __shared__ u32x4 Bhi[BNC * U + BNC / RPP], Blo[BNC * U + BNC / RPP];
+  auto unit = [](int row, int g) { return U * row + row / RPP + g; };
 
   const int64_t M = int64_t(1) << d.m, N = int64_t(1) << d.n, K = int64_t(1) << d.k;
-  const int tiles_n = (int)(N / BNC);
-  const int64_t tiles = (M / BM) * tiles_n;
-  const int64_t total = tiles * d.nb;
-  int64_t w = blockIdx.x;
-  int64_t logical = (total % 8 == 0) ? (w % 8) * (total / 8) + w / 8 : w;
-  const int64_t b = logical / tiles;
-  const int64_t t = logical % tiles;
-  const int64_t bm = t / tiles_n, bn = t % tiles_n;
+  int64_t b, bm, bn;
+  tile_of(blockIdx.x, M / BM, N / BNC, d.nb, b, bm, bn);
 
   const float sa = BF ? 1.f : scale_of(d.scale_a[b]), sb = BF ? 1.f : scale_of(d.scale_b[b]);
   // operands in split layout: a row of K complex is K / 4 groups of 32 bytes
@@ -356,22 +361,33 @@ __global__ __launch_bounds__(256) void k_cgemm_split(GemmDesc d) {
         aim[x][y][v] = 0.f;
       }
 
+  // chunk c: 32 consecutive chunks cover RPP rows x U groups, first the
+  // 16 hi parts then the 16 lo parts (hi and lo of a group are adjacent in
+  // memory, so a row's cache line is read by one instruction)
+  auto chunk = [](int c, int& row, int& g, int& lo) {
+    int j = c & 15;
+    lo = (c >> 4) & 1;
+    row = (c >> 5) * RPP + j / U;
+    g = j % U;
+  };
   u32x4 ra[RA], rb[RB];
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int r = 0; r < RA; ++r) {
       int c = tid + 256 * r;
       if (c < CHA) {
-        int row = c / (2 * GPR), gp = c % (2 * GPR);
-        ra[r] = A[(row * K + k0) / 2 + gp];
+        int row, g, lo;
+        chunk(c, row, g, lo);
+        ra[r] = A[(row * K + k0) / 2 + 2 * g + lo];
       }
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       int c = tid + 256 * r;
       if (c < CHB) {
-        int row = c / (2 * GPR), gp = c % (2 * GPR);
-        rb[r] = B[(row * K + k0) / 2 + gp];
+        int row, g, lo;
+        chunk(c, row, g, lo);
+        rb[r] = B[(row * K + k0) / 2 + 2 * g + lo];
       }
     }
   };
@@ -380,24 +396,24 @@ __global__ __launch_bounds__(256) void k_cgemm_split(GemmDesc d) {
     for (int r = 0; r < RA; ++r) {
       int c = tid + 256 * r;
       if (c < CHA) {
-        int row = c / (2 * GPR), gp = c % (2 * GPR);
-        int o = row * LDK + 8 * (gp >> 1);
-        if (gp & 1)
-          *reinterpret_cast<u32x4*>(&Alo[o]) = ra[r];
+        int row, g, lo;
+        chunk(c, row, g, lo);
+        if (lo)
+          Alo[unit(row, g)] = ra[r];
         else
-          *reinterpret_cast<u32x4*>(&Ahi[o]) = ra[r];
+          Ahi[unit(row, g)] = ra[r];
       }
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       int c = tid + 256 * r;
       if (c < CHB) {
-        int row = c / (2 * GPR), gp = c % (2 * GPR);
-        int o = row * LDK + 8 * (gp >> 1);
-        if (gp & 1)
-          *reinterpret_cast<u32x4*>(&Blo[o]) = rb[r];
+        int row, g, lo;
+        chunk(c, row, g, lo);
+        if (lo)
+          Blo[unit(row, g)] = rb[r];
         else
-          *reinterpret_cast<u32x4*>(&Bhi[o]) = rb[r];
+          Bhi[unit(row, g)] = rb[r];
       }
     }
   };
@@ -413,19 +429,19 @@ __global__ __launch_bounds__(256) void k_cgemm_split(GemmDesc d) {
     if (k0 + BKC < K) load(k0 + BKC);
 #pragma unroll
     for (int ch = 0; ch < BKC / 8; ++ch) {
-      const int ko = 16 * ch + 8 * h;  // halves offset of this lane's 8 k'
+      const int gl = 2 * ch + h;  // this lane's group: 8 k' = 4 complex
       u32x4 ah[C::TM], al[C::TM];
 #pragma unroll
       for (int x = 0; x < C::TM; ++x) {
-        int o = (arow0 + 32 * x) * LDK + ko;
-        ah[x] = *reinterpret_cast<const u32x4*>(&Ahi[o]);
-        al[x] = *reinterpret_cast<const u32x4*>(&Alo[o]);
+        int o = unit(arow0 + 32 * x, gl);
+        ah[x] = Ahi[o];
+        al[x] = Alo[o];
       }
 #pragma unroll
       for (int y = 0; y < C::TN; ++y) {
-        int o = (bcol0 + 32 * y) * LDK + ko;
-        u32x4 bh = *reinterpret_cast<const u32x4*>(&Bhi[o]);
-        u32x4 bl = *reinterpret_cast<const u32x4*>(&Blo[o]);
+        int o = unit(bcol0 + 32 * y, gl);
+        u32x4 bh = Bhi[o];
+        u32x4 bl = Blo[o];
         u32x4 bs = BF ? bh : times2048(bh);
         u32x4 rh = bform(bh, false), ih = bform(bh, true);
         u32x4 rl = bform(bl, false), il = bform(bl, true);
@@ -487,8 +503,9 @@ const CfgInfo kCfgs[] = {
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 const CfgInfo kSplitCfgs[] = {
     {128, 128, 16, "split_128x128x16"}, {128, 64, 16, "split_128x64x16"}, {64, 128, 16, "split_64x128x16"},
-    {64, 64, 16, "split_64x64x16"},     {128, 128, 8, "split_128x128x8"}, {128, 64, 8, "split_128x64x8"},
-    {64, 64, 8, "split_64x64x8"},       {256, 64, 16, "split_256x64x16"},
+    {64, 64, 16, "split_64x64x16"},     {128, 64, 32, "split_128x64x32"}, {128, 64, 64, "split_128x64x64"},
+    {64, 64, 8, "split_64x64x8"},       {128, 128, 32, "split_128x128x32"}, {64, 64, 32, "split_64x64x32"},
+    {64, 128, 32, "split_64x128x32"},
 };
 constexpr int kNumSplit = sizeof(kSplitCfgs) / sizeof(kSplitCfgs[0]);
 
@@ -545,10 +562,12 @@ void launch_cgemm(const GemmDesc& d, int mode, hipStream_t st) {
       case 1: run_split<128, 64, 16>(d, bf, st); break;
       case 2: run_split<64, 128, 16>(d, bf, st); break;
       case 3: run_split<64, 64, 16>(d, bf, st); break;
-      case 4: run_split<128, 128, 8>(d, bf, st); break;
-      case 5: run_split<128, 64, 8>(d, bf, st); break;
+      case 4: run_split<128, 64, 32>(d, bf, st); break;
+      case 5: run_split<128, 64, 64>(d, bf, st); break;
       case 6: run_split<64, 64, 8>(d, bf, st); break;
-      case 7: run_split<256, 64, 16>(d, bf, st); break;
+      case 7: run_split<128, 128, 32>(d, bf, st); break;
+      case 8: run_split<64, 64, 32>(d, bf, st); break;
+      case 9: run_split<64, 128, 32>(d, bf, st); break;
     }
     return;
   }
