@@ -74,6 +74,9 @@ def main():
                     help="comma list; the first is the headline value, the others are reported beside it")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache (JSON, keyed by mode and step shape)")
+    ap.add_argument("--workload", default="rqc30", choices=["rqc30", "rqc53"],
+                    help="rqc30: every slice per step; rqc53: a seeded sample of --slices slices")
+    ap.add_argument("--slices", type=int, default=8, help="rqc53: sampled slices per step")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -98,13 +101,20 @@ def main():
     from workload import make_workload
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    w = make_workload("rqc30")
+    from workload import sample_slice_ids
+    w = make_workload(args.workload)
     t0 = time.perf_counter()
     pr = P.prepare(w)
     plan = pr.plan()
     costs = P.tree_costs(pr.net, pr.path, pr.sliced)
     t_plan = time.perf_counter() - t0
-    n_slices = 1 << len(pr.sliced)
+    if args.workload == "rqc30":
+        n_slices = 1 << len(pr.sliced)
+        ids = None
+    else:
+        # the seeded subset of 2^10 slice ids, first --slices of them
+        ids = sample_slice_ids(len(pr.sliced), 1024, 3)[: args.slices]
+        n_slices = len(ids)
     info = plan.info()
     macs_slice = info["macs_per_slice"]
     flops_step = 8.0 * macs_slice * n_slices
@@ -114,6 +124,12 @@ def main():
 
     batch = plan.bind(batch=n_slices) if plan.workspace_size(n_slices) < 0.7 * torch.cuda.mem_get_info()[0] \
         else plan.bind()
+
+    def run_step(out, mode):
+        if ids is None:
+            plan.execute_range(0, n_slices, out, mode)
+        else:
+            plan.execute(ids, out, mode)
     log(f"bound: batch={batch}, workspace={plan.workspace_size(batch) / 2**30:.2f} GiB")
     ref = np.load(GOLDEN) if os.path.exists(GOLDEN) else None
 
@@ -125,17 +141,17 @@ def main():
         out = plan.new_output()
         for _ in range(args.warmup):
             out.zero_()
-            plan.execute_range(0, n_slices, out, mode)
+            run_step(out, mode)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             out.zero_()
-            plan.execute_range(0, n_slices, out, mode)
+            run_step(out, mode)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         res = {"tflops": flops_step * args.steps / dt / 1e12, "ms_per_step": 1e3 * dt / args.steps,
                "sec_per_slice": dt / args.steps / n_slices}
-        if ref is not None:
+        if ref is not None and args.workload == "rqc30":
             got = out.cpu().numpy()
             res["rel_l2_error"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         # the dominant kernel (the MFMA complex GEMM): live per-step HIP
@@ -143,7 +159,7 @@ def main():
         ms = np.zeros(len(steps))
         reps = 3
         for _ in range(reps):
-            ms += plan.profile_steps(0, mode)
+            ms += plan.profile_steps(0 if ids is None else int(ids[0]), mode)
         ms /= reps
         mf_flops, mf_ms, mf_launch, split_flops = 0.0, 0.0, 0, 0.0
         for k, st in enumerate(steps):
@@ -188,7 +204,7 @@ def main():
                                        r["rel_l2_error"] <= (1e-4 if m == "c64" else 5e-4))
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "rqc30":
         log("timing the CPU oracle on one slice ...")
         cpu = cpu_baseline()
         log(f"oracle: {cpu['sec_per_slice']:.2f} s/slice, {cpu['value']:.4f} TFLOP/s on "
@@ -207,8 +223,11 @@ def main():
         "vs_baseline": None,
         "dtype": {"c64": "c64", "split_f16": "f16x2", "split_bf16": "bf16x2"}[main_mode],
         "data": "synthetic",
-        "config": {"workload": "rqc30: 5x6 grid, 14 cycles, 6 open qubits (64 amplitudes), "
-                               "max rank 26, all slices per step",
+        "config": {"workload": ("rqc30: 5x6 grid, 14 cycles, 6 open qubits (64 amplitudes), "
+                                "max rank 26, all slices per step") if args.workload == "rqc30" else
+                               (f"rqc53: 6x9 grid minus one site, 20 cycles, 20 open qubits (2^20 "
+                                f"amplitudes), max rank 30, {n_slices} seeded slices per step"),
+                   "projected_seconds_all_slices": r0["sec_per_slice"] * 2.0 ** len(pr.sliced),
                    "slices": n_slices, "sliced_indices": len(pr.sliced), "batch": batch,
                    "log2_C_BS": round(costs.log2_sliced, 4), "overhead": round(costs.overhead, 5),
                    "macs_per_slice": macs_slice, "flops_per_step": flops_step,

@@ -21,7 +21,8 @@
  *   - SSA path: leaves are 0..L-1, the k-th contraction creates id L+k;
  *     path[2k], path[2k+1] are its two operands;
  *   - slice id s: bit j (LSB = 0) of s is the value of the sliced index
- *     S[j];
+ *     S[j]; slice ids are 64-bit, so when |S| > 64 the indices S[64..]
+ *     keep the value 0 (the addressable slices are the first 2^64);
  *   - output vector: one entry per assignment of the open indices, the
  *     first open index is the most significant bit; sliced open indices
  *     take their bits from the slice id (placement), the others are summed
@@ -216,8 +217,9 @@ typedef struct ltn_options {
  * open indices last, in output order), give every step its (m, k, n) bit
  * groups and kernel, and lay tensors out in a per-slice arena by liveness.
  * Errors: LTN_E_INVALID (index in more than two leaves, open index not
- * listed, path not an SSA cover, duplicate / unknown sliced id, rank > 62),
- * LTN_E_CAP (max_rank exceeded). */
+ * listed, path not an SSA cover, duplicate / unknown sliced id, more than
+ * 255 sliced indices, a tensor of rank > 40 after slicing), LTN_E_CAP
+ * (max_rank exceeded). */
 ltn_status ltn_plan_load(const ltn_network* net, const int32_t* path_ssa, int32_t n_sliced,
                          const int32_t* sliced_ids, const ltn_options* opt, ltn_plan** out);
 
@@ -261,7 +263,8 @@ ltn_status ltn_workspace_size(const ltn_plan* plan, int32_t batch, int32_t grad,
  * stream). Errors: LTN_E_NOMEM if not even one slice fits. */
 ltn_status ltn_bind(ltn_plan* plan, void* d_workspace, size_t bytes, int32_t grad, void* stream);
 
-/* Contract the listed slices (host array of n ids, each < 2^|S|) and
+/* Contract the listed slices (host array of n ids, each < 2^|S| when
+ * |S| < 64) and
  * ADD the result into d_out (complex128, 2^n_open entries, device).
  * Slices are summed in FP64, in batches of the bound batch size; within a
  * batch in ascending position, batches in call order. Asynchronous on the

@@ -47,8 +47,8 @@ extern "C" ltn_status ltn_plan_load(const ltn_network* net, const int32_t* path_
     require(net->leaf_data != nullptr, "leaf_data is NULL");
     const int32_t L = (int32_t)n.sets.size();
     require(L == 1 || path_ssa != nullptr, "path is NULL");
-    require(n_sliced >= 0 && n_sliced <= 63 && (n_sliced == 0 || sliced_ids),
-            "bad slicing set (at most 63 indices)");
+    require(n_sliced >= 0 && n_sliced <= 255 && (n_sliced == 0 || sliced_ids),
+            "bad slicing set (at most 255 indices)");
     auto p = new ltn_plan();
     std::unique_ptr<ltn_plan> guard(p);
     if (opt) p->opt = *opt;
@@ -178,8 +178,9 @@ extern "C" ltn_status ltn_plan_load(const ltn_network* net, const int32_t* path_
         return -1;
       };
       for (int32_t x : p->tensors[i].idx) lp.src_bit.push_back(srcbit(x));
+      // sliced axes whose slice-id bit is 64 or above always take value 0
       for (int32_t x : n.axes[i])
-        if (slice_bit[x] >= 0) {
+        if (slice_bit[x] >= 0 && slice_bit[x] < 64) {
           lp.sl_src_bit.push_back(srcbit(x));
           lp.sl_bit.push_back(slice_bit[x]);
         }
@@ -193,7 +194,7 @@ extern "C" ltn_status ltn_plan_load(const ltn_network* net, const int32_t* path_
     {
       const IdSet& R = p->tensors[p->root].idx;
       for (int32_t x : R) p->out_mask |= 1ull << (p->n_open - 1 - open_pos[x]);
-      for (int32_t j = 0; j < (int32_t)p->sliced.size(); ++j) {
+      for (int32_t j = 0; j < (int32_t)p->sliced.size() && j < 64; ++j) {
         int32_t x = p->sliced[j];
         if (open_pos[x] >= 0) p->out_sliced.push_back({j, p->n_open - 1 - open_pos[x]});
       }

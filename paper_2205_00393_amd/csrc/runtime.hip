@@ -395,15 +395,15 @@ static ltn_status execute_impl(ltn_plan* p, const uint64_t* ids, uint64_t begin,
     check_mode(mode);
     require(d_out != nullptr, "d_out is NULL");
     const int ns = (int)p->sliced.size();
-    const uint64_t lim = ns >= 64 ? ~0ull : (1ull << ns);
     if (range) {
       require(begin <= n, "range end before begin");
-      require(n <= lim, "slice range beyond 2^|S|");
+      require(ns >= 64 || n <= (1ull << ns), "slice range beyond 2^|S|");
       n = n - begin;
     } else {
       require(n == 0 || ids != nullptr, "slice_ids is NULL");
-      for (uint64_t i = 0; i < n; ++i)
-        require(ids[i] < lim, "slice id " + std::to_string(ids[i]) + " is not below 2^|S|");
+      if (ns < 64)
+        for (uint64_t i = 0; i < n; ++i)
+          require(ids[i] < (1ull << ns), "slice id " + std::to_string(ids[i]) + " is not below 2^|S|");
     }
     for (uint64_t off = 0; off < n; off += (uint64_t)r.B) {
       int nb = (int)std::min<uint64_t>((uint64_t)r.B, n - off);
@@ -447,8 +447,8 @@ extern "C" ltn_status ltn_execute_grad(ltn_plan* p, const uint64_t* ids, uint64_
     require(d_cot && d_angle_grad, "NULL argument");
     require(n == 0 || ids, "slice_ids is NULL");
     const int ns = (int)p->sliced.size();
-    const uint64_t lim = ns >= 64 ? ~0ull : (1ull << ns);
-    for (uint64_t i = 0; i < n; ++i) require(ids[i] < lim, "slice id is not below 2^|S|");
+    if (ns < 64)
+      for (uint64_t i = 0; i < n; ++i) require(ids[i] < (1ull << ns), "slice id is not below 2^|S|");
     double* lg = reinterpret_cast<double*>(r.ws + r.lay.leafgrad);
     launch_fill_zero(lg, al((size_t)r.n_pl * 64), r.st);
     const GatherDesc* gcot = reinterpret_cast<const GatherDesc*>(r.ws + r.lay.gd_gcot);

@@ -1,0 +1,69 @@
+"""Write oracle references for sampled slices of the 53-qubit workload.
+
+Calls only the oracle and the seeded workload generator: the oracle's own
+path search (randomised greedy, same rule and grid as the library's
+default), its slice finder at t = 30, and, for each of the first N slice
+ids of the seeded subset (seed 3), the plain tensordot contraction of that
+slice in complex128, sub-sliced at t = 29 to fit host memory (the extra
+sub-slice indices are summed over; sliced open indices are placed).
+Stores, per slice, 4096 amplitudes at seeded output positions (seed 5) and
+the squared norm of the whole 2^20-amplitude block.
+
+Usage: python tests/golden/make_rqc53_reference.py [N] [OUTDIR]
+Needs ~60 GiB of host memory and minutes per slice on 16 cores.
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import network as nw  # noqa: E402
+from oracle import planner as pl  # noqa: E402
+from workload import make_workload, sample_slice_ids  # noqa: E402
+
+ALPHAS, TAUS, SEEDS = (0.5, 1.0, 2.0), (0.0, 0.3, 1.0), 16
+T_SUB = 29
+N_POS = 4096
+
+
+def main():
+    n_slices = int(sys.argv[1]) if len(sys.argv) > 1 else 1
+    outdir = sys.argv[2] if len(sys.argv) > 2 else HERE
+    w = make_workload("rqc53")
+    net = nw.absorb_small(nw.circuit_network(w.circuit, w.open_qubits, w.closed_bits))
+    t0 = time.time()
+    path, S, trial = pl.path_search(net.indices, w.max_rank, (), ALPHAS, TAUS, SEEDS)
+    tree = pl.Tree(net.indices, path)
+    print(f"path search {time.time() - t0:.1f}s trial {trial} |S|={len(S)}", flush=True)
+    S2 = pl.slice_finder(tree, T_SUB, pre=S)
+    extra = S2[len(S):]
+    print(f"sub-slicing at t={T_SUB}: {len(extra)} extra indices", flush=True)
+    ids = [int(x) for x in sample_slice_ids(len(S), 1024, 3)[:n_slices]]
+    pos = np.sort(np.random.default_rng(5).choice(1 << len(net.open_ids), N_POS, replace=False))
+    rec = dict(workload="rqc53", trial=trial, sliced=[int(x) for x in S], extra=[int(x) for x in extra],
+               t_sub=T_SUB, path_sha256=hashlib.sha256(np.asarray(path, dtype=np.int32).tobytes()).hexdigest(),
+               slices=[])
+    amps = []
+    for s in ids:
+        out = np.zeros(1 << len(net.open_ids), dtype=np.complex128)
+        t1 = time.time()
+        for e in range(1 << len(extra)):
+            s2 = s | (e << len(S))
+            blk = nw.slice_output(net, path, S2, s2)
+            out[nw.place(net, S2, s2, blk)] += blk
+            print(f"slice {s} sub-slice {e} {time.time() - t1:.1f}s", flush=True)
+        rec["slices"].append(dict(id=str(s), norm2=float(np.sum(np.abs(out) ** 2))))
+        amps.append(out[pos])
+    np.savez(os.path.join(outdir, "rqc53_slices.npz"), positions=pos, amplitudes=np.asarray(amps))
+    json.dump(rec, open(os.path.join(outdir, "rqc53_slices.json"), "w"), indent=1)
+    print(json.dumps(rec)[:400], flush=True)
+
+
+if __name__ == "__main__":
+    main()

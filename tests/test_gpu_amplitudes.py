@@ -225,3 +225,33 @@ def test_rqc30_split_full_size(torch, mode):
     err = rel_l2(out.cpu().numpy(), ref)
     banner(f"rqc30 {mode} rel err {err:.3e}")
     assert err < TOL_SPLIT
+
+
+def test_rqc53_sampled_slice(torch):
+    """53-qubit workload at full size (t = 30, |S| = 68): one sampled slice
+    (2^20 amplitudes) against the oracle's complex128 contraction of the
+    same slice, stored by tests/golden/make_rqc53_reference.py (4096 seeded
+    amplitudes and the block's squared norm)."""
+    import paper_2205_00393_amd as P
+    path = os.path.join(GOLDEN, "rqc53_slices.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden rqc53 slices not generated")
+    ref = np.load(path)
+    meta = json.load(open(os.path.join(GOLDEN, "rqc53_slices.json")))
+    w = make_workload("rqc53")
+    banner("rqc53 plan")
+    pr = P.prepare(w)
+    assert pr.sliced == meta["sliced"]
+    plan = pr.plan()
+    plan.bind(batch=1)
+    for j, rec in enumerate(meta["slices"]):
+        s = int(rec["id"])
+        banner(f"rqc53 slice {s}")
+        out = plan.execute([s])
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        err = rel_l2(got[ref["positions"]], ref["amplitudes"][j])
+        n2 = float(np.sum(np.abs(got) ** 2))
+        banner(f"rqc53 slice {s}: sampled rel err {err:.3e}, norm2 {n2:.6e} vs {rec['norm2']:.6e}")
+        assert err < TOL_C64
+        assert abs(n2 - rec["norm2"]) < 2 * TOL_C64 * rec["norm2"]

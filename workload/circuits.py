@@ -157,12 +157,18 @@ def sample_bitstrings(n_bits: int, count: int, seed: int) -> np.ndarray:
 
 
 def sample_slice_ids(n_sliced: int, count: int, seed: int) -> np.ndarray:
-    """Sorted subset of slice ids in [0, 2**n_sliced); all ids if fewer."""
+    """Sorted subset of slice ids in [0, 2**n_sliced); all ids if fewer.
+
+    Slice ids are 64-bit: for more than 62 sliced indices the ids are drawn
+    uniformly from [0, 2**62) (the higher sliced indices keep value 0)."""
     total = 1 << n_sliced
     if total <= count:
         return np.arange(total, dtype=np.uint64)
     rng = np.random.default_rng(seed)
-    ids = rng.choice(total, size=count, replace=False)
+    if n_sliced <= 62:
+        ids = rng.choice(total, size=count, replace=False)
+    else:
+        ids = np.unique(rng.integers(0, 1 << 62, size=count, dtype=np.int64))
     return np.sort(np.asarray(ids, dtype=np.uint64))
 
 
