@@ -300,6 +300,22 @@ ltn_status ltn_autotune(ltn_plan* plan, int32_t mode, const char* cache_path);
  * n_steps floats of milliseconds into ms_out. Synchronises the stream. */
 ltn_status ltn_profile_steps(ltn_plan* plan, uint64_t first_slice, int32_t mode, float* ms_out);
 
+/* Bit permutation of a batch of complex64 tensors (the layout change a
+ * transpose-transpose-GEMM-transpose contraction applies around each GEMM,
+ * Sec. 2.1.2 and Sec. 5.3.1; the plan's own steps never need it because
+ * their layouts make every operand GEMM-ready and fold the output
+ * transposition into the GEMM's store):
+ *     out[b][y] = in[b][x]   with bit perm[j] of y equal to bit j of x
+ * (bit 0 = fastest-varying). d_in / d_out: device complex64 arrays of
+ * batch * 2^rank elements, tensor b at offset b * 2^rank; they must not
+ * overlap. perm: host array of rank entries, a permutation of 0..rank-1.
+ * Staged through LDS tiles that cover the lowest 5 bits of both sides, so
+ * reads and writes are coalesced. Asynchronous on `stream` (hipStream_t as
+ * void*; NULL = default stream). Errors: LTN_E_INVALID (rank > 40, perm not
+ * a permutation, in == out, batch < 1). */
+ltn_status ltn_permute(const void* d_in, void* d_out, int32_t rank, const int32_t* perm,
+                       int64_t batch, void* stream);
+
 /* Kernel chosen for a step in a mode after ltn_bind / ltn_autotune:
  * kind 0 = generic VALU kernel (tk threads per output), 1 = complex64 MFMA
  * GEMM, 2 = split-precision MFMA GEMM; cfg = tile configuration of that

@@ -6,7 +6,7 @@ arguments and lends PyTorch device memory and streams.
 """
 from ._lib import LtnError, lib, MODES
 from .network import (Network, greedy_path, tree_costs, tree_stem, slice_finder, path_search)
-from .plan import Plan, Prepared, prepare
+from .plan import Plan, Prepared, prepare, permute
 
 __all__ = ["LtnError", "lib", "MODES", "Network", "greedy_path", "tree_costs", "tree_stem",
-           "slice_finder", "path_search", "Plan", "Prepared", "prepare"]
+           "slice_finder", "path_search", "Plan", "Prepared", "prepare", "permute"]

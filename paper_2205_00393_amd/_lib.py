@@ -93,6 +93,7 @@ SIGNATURES = {
     "ltn_autotune": [P, I32, C.c_char_p],
     "ltn_profile_steps": [P, U64, I32, C.POINTER(C.c_float)],
     "ltn_step_kernel": [P, I32, I32, I32P, I32P, I32P, I32P],
+    "ltn_permute": [P, P, I32, I32P, C.c_int64, P],
     "ltn_plan_free": [P],
     "ltn_last_error": [],
     "ltn_version": [],

@@ -34,6 +34,7 @@ SOURCES = [
     ("runtime.hip", "hip"),
     ("k_misc.hip", "hip"),
     ("k_mfma.hip", "hip"),
+    ("k_permute.hip", "hip"),
 ]
 
 

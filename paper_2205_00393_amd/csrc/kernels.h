@@ -83,6 +83,18 @@ struct GemmDesc {
   const uint32_t* scale_b;   //              and of B
   uint32_t* scale_c;         // if set: record the output's per-slice max |x|
 };
+// Tile plan of a bit permutation (built on the host by ltn_permute).
+struct PermuteDesc {
+  int32_t rank, n_tile, n_outer;
+  int64_t batch;
+  int8_t tile_src[16];   // tile bit k -> source bit (ascending)
+  int8_t tile_dst[16];   // destination-order rank r -> destination bit
+  int8_t dst_tile[16];   // destination-order rank r -> tile bit
+  int8_t outer_src[64];  // outer bit k -> source bit
+  int8_t outer_dst[64];  // outer bit k -> destination bit
+};
+void launch_permute(const float2* in, float2* out, const PermuteDesc& d, hipStream_t st);
+
 int gemm_config_count(int mode);
 bool gemm_config_fits(int cfg, int m, int k, int n, int mode);
 const char* gemm_config_name(int cfg, int mode);

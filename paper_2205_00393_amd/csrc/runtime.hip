@@ -723,3 +723,53 @@ extern "C" ltn_status ltn_step_kernel(const ltn_plan* p, int32_t step, int32_t m
     if (tk) *tk = c.tk;
   });
 }
+
+extern "C" ltn_status ltn_permute(const void* d_in, void* d_out, int32_t rank, const int32_t* perm,
+                                  int64_t batch, void* stream) {
+  return guarded([&] {
+    require(d_in && d_out, "NULL buffer");
+    require(d_in != d_out, "ltn_permute does not work in place");
+    require(rank >= 0 && rank <= 40, "rank must be in 0..40");
+    require(batch >= 1, "batch must be >= 1");
+    require(rank == 0 || perm != nullptr, "perm is NULL");
+    std::vector<int> inv(rank, -1);
+    for (int j = 0; j < rank; ++j) {
+      require(perm[j] >= 0 && perm[j] < rank && inv[perm[j]] < 0, "perm is not a permutation");
+      inv[perm[j]] = j;
+    }
+    PermuteDesc d{};
+    d.rank = rank;
+    d.batch = batch;
+    const int t = std::min(rank, 5);
+    std::vector<char> in_tile(rank, 0);
+    for (int j = 0; j < t; ++j) in_tile[j] = 1;          // lowest source bits
+    for (int y = 0; y < t; ++y) in_tile[inv[y]] = 1;     // sources of the lowest destination bits
+    int nt = 0;
+    for (int j = 0; j < rank; ++j) nt += in_tile[j];
+    for (int j = 0; j < rank && nt < std::min(rank, 12); ++j)
+      if (!in_tile[j]) {
+        in_tile[j] = 1;  // fill the tile up to 4096 elements with the next source bits
+        ++nt;
+      }
+    std::vector<int> tsrc, outer;
+    for (int j = 0; j < rank; ++j) (in_tile[j] ? tsrc : outer).push_back(j);
+    d.n_tile = (int)tsrc.size();
+    d.n_outer = (int)outer.size();
+    for (int k = 0; k < d.n_tile; ++k) d.tile_src[k] = (int8_t)tsrc[k];
+    // destination order of the tile bits
+    std::vector<std::pair<int, int>> dt;
+    for (int k = 0; k < d.n_tile; ++k) dt.push_back({perm[tsrc[k]], k});
+    std::sort(dt.begin(), dt.end());
+    for (int r = 0; r < d.n_tile; ++r) {
+      d.tile_dst[r] = (int8_t)dt[r].first;
+      d.dst_tile[r] = (int8_t)dt[r].second;
+    }
+    for (int k = 0; k < d.n_outer; ++k) {
+      d.outer_src[k] = (int8_t)outer[k];
+      d.outer_dst[k] = (int8_t)perm[outer[k]];
+    }
+    launch_permute(reinterpret_cast<const float2*>(d_in), reinterpret_cast<float2*>(d_out), d,
+                   reinterpret_cast<hipStream_t>(stream));
+    check_launch();
+  });
+}

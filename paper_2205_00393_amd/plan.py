@@ -195,3 +195,17 @@ def prepare(workload, alphas=SEARCH_ALPHAS, taus=SEARCH_TAUS, n_seeds=SEARCH_SEE
     t = w.max_rank if w.max_rank is not None else -1
     path, S, trial = path_search(net, t, pre, alphas, taus, n_seeds, seed_base)
     return Prepared(w, net, path, S, trial, pre)
+
+
+def permute(x, perm, out=None, stream=None):
+    """Bit permutation of complex64 CUDA tensors: x has shape [batch, 2^rank]
+    (or [2^rank]); out[b][y] = x[b][x_] with bit perm[j] of y = bit j of x_."""
+    torch = _torch()
+    rank = len(perm)
+    xx = x.contiguous()
+    batch = xx.numel() >> rank
+    if out is None:
+        out = torch.empty_like(xx)
+    L.check(L.lib().ltn_permute(C.c_void_p(xx.data_ptr()), C.c_void_p(out.data_ptr()), rank,
+                                L.i32_array(list(perm)), batch, _stream_ptr(stream)))
+    return out

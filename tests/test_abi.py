@@ -1,0 +1,36 @@
+"""The C ABI: libltn loads without a GPU and exports every function that
+include/ltn.h declares (no device call is made here)."""
+import ctypes
+import os
+import re
+
+from paper_2205_00393_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "ltn.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ltn_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    names = declared()
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+
+
+def test_binding_covers_the_header():
+    assert set(declared()) == set(_lib.SIGNATURES)
+
+
+def test_error_reporting_without_gpu():
+    L = _lib.lib()
+    assert L.ltn_version().decode().startswith("ltn")
+    st = L.ltn_plan_describe(None, None)
+    assert st == -1 and "NULL" in L.ltn_last_error().decode()
+    # device entry points refuse an unbound or NULL plan before touching HIP
+    assert L.ltn_execute_range(None, 0, 1, 0, None) == -5
