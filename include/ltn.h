@@ -196,6 +196,49 @@ ltn_status ltn_path_search(const ltn_network* net, int32_t t, const int32_t* pre
                            const ltn_search_opts* opts, int32_t* path_out, int32_t* S_out,
                            int32_t cap, int32_t* n_sliced, int32_t* best_trial);
 
+/* Slice refiner (Sec. 4.3, Algorithms 2-4): simulated annealing over edge
+ * replacements at fixed |S|. Each iteration picks a slot of S (beyond the
+ * first n_fixed, which never move) with a keyed uniform draw; the critical
+ * tensors of its index are the tensors holding it (leaves included) whose
+ * rank after S equals t (Algorithm 3); the candidates are the unsliced
+ * indices held by all of them (Algorithm 4), tried in ascending id, each
+ * replacing the slot's current occupant: a move that lowers C(B,S) (Eq. 4)
+ * is taken, a costlier one with probability exp((C_ori - C_new)/C_ori/T).
+ * An index with no critical tensor in its lifetime is dropped from S. T
+ * starts at t0 and is multiplied by alpha every iters_per_temp iterations
+ * until T < tf. Draws: slot = n_fixed + floor(u (|S| - n_fixed)) with
+ * u = keyed_uniform(seed, iteration, 0, 0); uphill acceptance draws
+ * keyed_uniform(seed, iteration, 1, candidate id) (SplitMix64 keyed as in
+ * ltn_greedy_path). Every set it visits meets the cap; the best seen (lowest
+ * C(B,S), first reached) is returned in S_out (capacity n_in; the order of
+ * kept slots is preserved, so bit j of a slice id stays the value of S[j]).
+ * Errors: LTN_E_CAP if S_in does not meet the cap t; LTN_E_INVALID for a
+ * repeated id or bad parameters (alpha outside (0,1), non-positive t0/tf,
+ * iters_per_temp < 1, n_fixed outside 0..n_in). */
+typedef struct ltn_refine_opts {
+  double t0;              /* initial temperature (1.0)                     */
+  double alpha;           /* cooling factor (0.98)                         */
+  double tf;              /* final temperature (1e-3)                      */
+  int32_t iters_per_temp; /* iterations at each temperature (1)            */
+  int32_t n_fixed;        /* leading entries of S that are never replaced  */
+  uint64_t seed;
+} ltn_refine_opts;
+typedef struct ltn_refine_stats {
+  int32_t iterations, proposals, accepted, dropped;
+} ltn_refine_stats;
+ltn_status ltn_slice_refine(const ltn_network* net, const int32_t* path, int32_t t,
+                            const int32_t* S_in, int32_t n_in, const ltn_refine_opts* opts,
+                            int32_t* S_out, int32_t* n_out, ltn_refine_stats* stats);
+
+/* Greedy least-overhead slicer, the strategy the paper attributes to
+ * cotengra (Sec. 2.2), for comparison with Algorithm 1: starting from pre,
+ * while some tree tensor has rank > t after S, append the unsliced index of
+ * such tensors that gives the smallest C(B,S) (Eq. 4); ties: held by the
+ * most tensors above t, then the smaller id. S_out capacity = cap. */
+ltn_status ltn_slice_greedy_overhead(const ltn_network* net, const int32_t* path, int32_t t,
+                                     const int32_t* pre, int32_t n_pre, int32_t* S_out,
+                                     int32_t cap, int32_t* n_sliced);
+
 /* ------------------------------------------------------------------------
  * Plans and execution.
  * ---------------------------------------------------------------------- */

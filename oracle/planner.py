@@ -30,6 +30,31 @@ Tie-breaks of Algorithm 1 (the paper does not give them):
 * off-stem tensors still above t afterwards (post-order, SSA order): add
   their unsliced index with the longest whole-tree lifetime (then smaller
   id) until they fit.
+
+Slice refiner (Sec. 4.3, Algorithms 2-4), readings where the paper is
+silent:
+* lifetime of an index = every tree tensor holding it (leaves included);
+  ``dim`` = rank after removing the current S; critical tensors of a sliced
+  index = tensors of its lifetime whose dim equals t (Algorithm 3);
+* candidates = the indices common to all its critical tensors (Algorithm 4),
+  minus the current S, in ascending id;
+* a sliced index whose lifetime holds no critical tensor is dropped from S
+  (it reduces no tensor to the cap, Sec. 4.3), which lowers C(B,S);
+* candidate moves act on the chosen slot in turn: each proposal replaces
+  the slot's current occupant, so the cap is kept by construction;
+* T starts at t0 and is multiplied by alpha after every ``iters_per_temp``
+  iterations; the loop runs until T < tf (at least once); acceptance of a
+  costlier set: keyed uniform < exp((C_ori - C_new) / C_ori / T), with the
+  two big integers rounded to doubles; the best set seen is returned;
+* the first ``n_fixed`` entries of S (pre-sliced indices) are never moved.
+* random draws: iteration i picks slot n_fixed + floor(u (|S| - n_fixed))
+  with u = keyed_uniform(seed, i, 0, 0); candidate c is accepted uphill
+  when keyed_uniform(seed, i, 1, c) < p.
+
+Greedy-overhead slicer (the strategy attributed to cotengra in Sec. 2.2):
+while some tensor is above t, slice the index, among those of tensors above
+t, whose addition gives the smallest C(B,S); ties: held by the most
+tensors above t, then the smaller id.
 """
 from __future__ import annotations
 
@@ -264,3 +289,96 @@ def path_search(leaf_indices, t: int, pre: Sequence[int] = (), alphas=(1.0,), ta
                     best = (key, p, S, trial)
                 trial += 1
     return best[1], best[2], best[3]
+
+
+def critical_tensors(tree: Tree, S: Sequence[int], index: int, t: int) -> List[int]:
+    """Algorithm 3: the tensors in the lifetime of ``index`` whose rank after
+    slicing S equals the target t."""
+    Sset = set(S)
+    return [v for v in tree.lifetime(index) if len(tree.sets[v] - Sset) == t]
+
+
+def candidate_indices(tree: Tree, crit: Sequence[int], S: Sequence[int]) -> List[int]:
+    """Algorithm 4: indices held by every critical tensor, excluding the
+    sliced ones; ascending id."""
+    cand = set(tree.sets[crit[0]])
+    for v in crit:
+        cand &= tree.sets[v]
+    return sorted(cand - set(S))
+
+
+def fits(tree: Tree, S: Sequence[int], t: int) -> bool:
+    Sset = set(S)
+    return all(len(s - Sset) <= t for s in tree.sets)
+
+
+def slice_refine(tree: Tree, t: int, S: Sequence[int], n_fixed: int = 0, t0: float = 1.0,
+                 alpha: float = 0.98, tf: float = 1e-3, iters_per_temp: int = 1,
+                 seed: int = 0) -> Tuple[List[int], dict]:
+    """Algorithm 2 (simulated annealing over edge replacements). Returns the
+    best slicing set seen and counters (iterations, proposals, accepted,
+    dropped)."""
+    if not fits(tree, S, t):
+        raise ValueError("the input slicing set does not meet the cap")
+    cur = list(S)
+    cur_c = tree.sliced_cost(cur)
+    best, best_c = list(cur), cur_c
+    stats = {"iterations": 0, "proposals": 0, "accepted": 0, "dropped": 0}
+    T = t0
+    it = 0
+    while True:
+        for _ in range(iters_per_temp):
+            free = len(cur) - n_fixed
+            if free <= 0:
+                break
+            u = keyed_uniform(seed, it, 0, 0)
+            slot = n_fixed + min(int(u * free), free - 1)
+            crit = critical_tensors(tree, cur, cur[slot], t)
+            if not crit:
+                del cur[slot]
+                cur_c = tree.sliced_cost(cur)
+                stats["dropped"] += 1
+            else:
+                for c in candidate_indices(tree, crit, cur):
+                    prop = list(cur)
+                    prop[slot] = c
+                    new_c = tree.sliced_cost(prop)
+                    stats["proposals"] += 1
+                    if new_c < cur_c:
+                        take = True
+                    else:
+                        p = math.exp(-(float(new_c - cur_c) / float(cur_c)) / T)
+                        take = keyed_uniform(seed, it, 1, c) < p
+                    if take:
+                        cur, cur_c = prop, new_c
+                        stats["accepted"] += 1
+                    if cur_c < best_c:
+                        best, best_c = list(cur), cur_c
+            if cur_c < best_c:
+                best, best_c = list(cur), cur_c
+            it += 1
+        stats["iterations"] = it
+        T = T * alpha
+        if T < tf or len(cur) <= n_fixed:
+            break
+    return best, stats
+
+
+def greedy_overhead_slicer(tree: Tree, t: int, pre: Sequence[int] = ()) -> List[int]:
+    """Greedy slicing by least overhead: add, one at a time, the index that
+    gives the smallest C(B,S) among the unsliced indices of tensors above t
+    (ties: most tensors above t holding it, then smaller id)."""
+    S = list(pre)
+    if t < 0:
+        return S
+    while True:
+        Sset = set(S)
+        big = [v for v, s in enumerate(tree.sets) if len(s - Sset) > t]
+        if not big:
+            return S
+        count: Dict[int, int] = {}
+        for v in big:
+            for x in tree.sets[v] - Sset:
+                count[x] = count.get(x, 0) + 1
+        pick = min(count, key=lambda x: (tree.sliced_cost(S + [x]), -count[x], x))
+        S.append(pick)

@@ -5,8 +5,9 @@ execution, both in libltn (C ABI in include/ltn.h); this package marshals
 arguments and lends PyTorch device memory and streams.
 """
 from ._lib import LtnError, lib, MODES
-from .network import (Network, greedy_path, tree_costs, tree_stem, slice_finder, path_search)
+from .network import (Network, greedy_path, tree_costs, tree_stem, slice_finder, path_search,
+                      slice_refine, slice_greedy_overhead)
 from .plan import Plan, Prepared, prepare, permute
 
 __all__ = ["LtnError", "lib", "MODES", "Network", "greedy_path", "tree_costs", "tree_stem",
-           "slice_finder", "path_search", "Plan", "Prepared", "prepare", "permute"]
+           "slice_finder", "path_search", "slice_refine", "slice_greedy_overhead", "Plan", "Prepared", "prepare", "permute"]

@@ -43,6 +43,16 @@ class SearchOpts(C.Structure):
                 ("n_seeds", C.c_int32), ("seed_base", C.c_uint64)]
 
 
+class RefineOpts(C.Structure):
+    _fields_ = [("t0", C.c_double), ("alpha", C.c_double), ("tf", C.c_double),
+                ("iters_per_temp", C.c_int32), ("n_fixed", C.c_int32), ("seed", C.c_uint64)]
+
+
+class RefineStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("proposals", C.c_int32), ("accepted", C.c_int32),
+                ("dropped", C.c_int32)]
+
+
 class Options(C.Structure):
     _fields_ = [("max_rank", C.c_int32), ("batch", C.c_int32), ("fat_threshold", C.c_int32),
                 ("reserved", C.c_int32)]
@@ -81,6 +91,9 @@ SIGNATURES = {
     "ltn_slice_finder": [C.POINTER(Network), I32P, I32, I32P, I32, I32P, I32, I32P],
     "ltn_path_search": [C.POINTER(Network), I32, I32P, I32, C.POINTER(SearchOpts), I32P, I32P, I32,
                         I32P, I32P],
+    "ltn_slice_refine": [C.POINTER(Network), I32P, I32, I32P, I32, C.POINTER(RefineOpts), I32P,
+                         I32P, C.POINTER(RefineStats)],
+    "ltn_slice_greedy_overhead": [C.POINTER(Network), I32P, I32, I32P, I32, I32P, I32, I32P],
     "ltn_plan_load": [C.POINTER(Network), I32P, I32, I32P, C.POINTER(Options), C.POINTER(P)],
     "ltn_plan_describe": [P, C.POINTER(PlanInfo)],
     "ltn_plan_step": [P, I32, C.POINTER(StepInfo)],

@@ -19,6 +19,26 @@ double BigSum::log2() const {
   return -INFINITY;
 }
 
+double BigSum::to_double() const {
+  int top = -1;
+  for (size_t i = w.size(); i-- > 0;)
+    if (w[i]) {
+      top = (int)i * 64 + 63 - __builtin_clzll(w[i]);
+      break;
+    }
+  if (top < 0) return 0.0;
+  if (top < 53) return (double)w[0];  // exact
+  auto bit = [&](int i) -> uint64_t { return (w[(size_t)i / 64] >> (i % 64)) & 1; };
+  const int low = top - 52;  // weight of the last kept bit
+  uint64_t m = 0;
+  for (int i = top; i >= low; --i) m = (m << 1) | bit(i);
+  const bool half = bit(low - 1) != 0;
+  bool sticky = false;
+  for (int i = low - 2; i >= 0 && !sticky; --i) sticky = bit(i) != 0;
+  if (half && (sticky || (m & 1))) ++m;
+  return std::ldexp((double)m, low);
+}
+
 IdSet set_xor(const IdSet& a, const IdSet& b) {
   IdSet r;
   std::set_symmetric_difference(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(r));

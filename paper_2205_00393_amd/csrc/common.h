@@ -67,6 +67,7 @@ struct BigSum {
     return 0;
   }
   double log2() const;
+  double to_double() const;  // correctly rounded, ties to even
   void to_words(uint64_t* out, int n) const {
     for (int i = 0; i < n; ++i) out[i] = i < (int)w.size() ? w[i] : 0;
   }
@@ -111,5 +112,17 @@ std::vector<int32_t> greedy(const std::vector<IdSet>& leaves, const IdSet& exclu
                             double tau, uint64_t seed);
 std::vector<int32_t> slice_finder(const std::vector<IdSet>& leaves, const int32_t* path, int t,
                                   const std::vector<int32_t>& pre);
+
+struct RefineParams {
+  double t0 = 1.0, alpha = 0.98, tf = 1e-3;
+  int iters_per_temp = 1, n_fixed = 0;
+  uint64_t seed = 0;
+};
+struct RefineStats {
+  int32_t iterations = 0, proposals = 0, accepted = 0, dropped = 0;
+};
+std::vector<int32_t> slice_refine(const Tree& tree, int t, const std::vector<int32_t>& S,
+                                  const RefineParams& p, RefineStats* st);
+std::vector<int32_t> slice_greedy_overhead(const Tree& tree, int t, const std::vector<int32_t>& pre);
 
 }  // namespace ltn

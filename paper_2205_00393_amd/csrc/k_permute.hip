@@ -14,6 +14,7 @@ namespace {
 
 constexpr int kTileBits = 12;  // up to 4096 elements (32 KiB) per tile
 
+// bit k of v goes to bit pos[k]
 __device__ __forceinline__ uint64_t spread(uint64_t v, const int8_t* pos, int n) {
   uint64_t r = 0;
   for (int k = 0; k < n; ++k) r |= ((v >> k) & 1) << pos[k];
@@ -21,12 +22,21 @@ __device__ __forceinline__ uint64_t spread(uint64_t v, const int8_t* pos, int n)
 }
 
 // Bit maps are linear in the bits, so each tile-local map is the OR of a
-// table over the low 6 tile bits and one over the high 6.
-__global__ __launch_bounds__(256) void k_permute(const float2* __restrict__ in, float2* __restrict__ out,
-                                                 PermuteDesc d) {
-  __shared__ float2 tile[1 << kTileBits];
+// table over the low 6 tile bits and one over the high 6. Every thread
+// handles tile elements tid + 256 i (i < 16): their offsets are fixed per
+// thread and computed once; a block's 16 loads are issued back to back.
+// LDS slot of tile element l: l with its low 5 bits XORed by swz_tab[l >> 5],
+// chosen on the host so that the 32 elements one half-wave reads in
+// destination order fall into 32 distinct bank pairs.
+constexpr int kThreads = 256, kPer = (1 << kTileBits) / kThreads;
+
+// Elements are moved as 64-bit words (pure data movement, bit-exact).
+__global__ __launch_bounds__(kThreads) void k_permute(const uint64_t* __restrict__ in,
+                                                      uint64_t* __restrict__ out, PermuteDesc d) {
+  __shared__ uint64_t tile[1 << kTileBits];
   __shared__ uint64_t src_lo[64], src_hi[64], dst_lo[64], dst_hi[64];
   __shared__ uint16_t map_lo[64], map_hi[64];
+  __shared__ uint8_t swz_tab[1 << (kTileBits - 5)];
   const int nlo = d.n_tile < 6 ? d.n_tile : 6, nhi = d.n_tile - nlo;
   for (int e = threadIdx.x; e < 64; e += blockDim.x) {
     src_lo[e] = spread((uint64_t)e, d.tile_src, nlo);
@@ -39,24 +49,49 @@ __global__ __launch_bounds__(256) void k_permute(const float2* __restrict__ in, 
     map_lo[e] = (uint16_t)ml;
     map_hi[e] = (uint16_t)mh;
   }
+  for (int h = threadIdx.x; h < (1 << (kTileBits - 5)); h += blockDim.x) {
+    int m = 0;
+    for (int k = 0; k < kTileBits - 5; ++k)
+      if ((h >> k) & 1) m ^= d.swz[k];
+    swz_tab[h] = (uint8_t)m;
+  }
   __syncthreads();
-  const int64_t per = int64_t(1) << d.rank;
-  const int64_t outer = int64_t(1) << d.n_outer;
   const int nt = 1 << d.n_tile;
   const int lomask = (1 << nlo) - 1;
+  const int tid = threadIdx.x;
+  uint64_t soff[kPer], doff[kPer];
+  int wslot[kPer], rslot[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int l = tid + kThreads * i;
+    if (l < nt) {
+      soff[i] = src_lo[l & lomask] | src_hi[l >> nlo];
+      doff[i] = dst_lo[l & lomask] | dst_hi[l >> nlo];
+      wslot[i] = l ^ swz_tab[l >> 5];
+      const int t = map_lo[l & lomask] | map_hi[l >> nlo];
+      rslot[i] = t ^ swz_tab[t >> 5];
+    }
+  }
+  const int64_t per = int64_t(1) << d.rank;
+  const int64_t outer = int64_t(1) << d.n_outer;
   for (int64_t blk = blockIdx.x; blk < outer * d.batch; blk += gridDim.x) {
     const int64_t b = blk / outer, o = blk % outer;
-    const uint64_t sbase = spread((uint64_t)o, d.outer_src, d.n_outer);
-    const uint64_t dbase = spread((uint64_t)o, d.outer_dst, d.n_outer);
-    const float2* src = in + b * per;
-    float2* dst = out + b * per;
-    // read in source order (tile bit k = source bit tile_src[k], ascending)
-    for (int l = threadIdx.x; l < nt; l += blockDim.x)
-      tile[l] = src[sbase | src_lo[l & lomask] | src_hi[l >> nlo]];
+    const uint64_t* src = in + b * per + spread((uint64_t)o, d.outer_src, d.n_outer);
+    uint64_t* dst = out + b * per + spread((uint64_t)o, d.outer_dst, d.n_outer);
+    uint64_t v[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i)
+      if (tid + kThreads * i < nt) v[i] = __builtin_nontemporal_load(&src[soff[i]]);
+#pragma unroll
+    for (int i = 0; i < kPer; ++i)
+      if (tid + kThreads * i < nt) tile[wslot[i]] = v[i];
     __syncthreads();
-    // write in destination order
-    for (int q = threadIdx.x; q < nt; q += blockDim.x)
-      dst[dbase | dst_lo[q & lomask] | dst_hi[q >> nlo]] = tile[map_lo[q & lomask] | map_hi[q >> nlo]];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i)
+      if (tid + kThreads * i < nt) v[i] = tile[rslot[i]];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i)
+      if (tid + kThreads * i < nt) __builtin_nontemporal_store(v[i], &dst[doff[i]]);
     __syncthreads();
   }
 }
@@ -66,7 +101,8 @@ __global__ __launch_bounds__(256) void k_permute(const float2* __restrict__ in, 
 void launch_permute(const float2* in, float2* out, const PermuteDesc& d, hipStream_t st) {
   int64_t blocks = (int64_t(1) << d.n_outer) * d.batch;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_permute, dim3((unsigned)blocks), dim3(256), 0, st, in, out, d);
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)blocks), dim3(kThreads), 0, st, reinterpret_cast<const uint64_t*>(in),
+                     reinterpret_cast<uint64_t*>(out), d);
 }
 
 }  // namespace ltn

@@ -92,6 +92,7 @@ struct PermuteDesc {
   int8_t dst_tile[16];   // destination-order rank r -> tile bit
   int8_t outer_src[64];  // outer bit k -> source bit
   int8_t outer_dst[64];  // outer bit k -> destination bit
+  uint8_t swz[8];        // tile bit 5 + k -> XOR mask on the low 5 bits of its LDS slot
 };
 void launch_permute(const float2* in, float2* out, const PermuteDesc& d, hipStream_t st);
 

@@ -1,6 +1,7 @@
 // Host planner: greedy contraction path, contraction tree and its costs
-// (Eq. (1), (2), (4)), the stem, lifetimes and the slice finder
-// (Algorithm 1) with a fix-up for off-stem tensors.
+// (Eq. (1), (2), (4)), the stem, lifetimes, the slice finder (Algorithm 1)
+// with a fix-up for off-stem tensors, the slice refiner (Algorithms 2-4)
+// and a greedy least-overhead slicer for comparison.
 //
 // Compiled with -ffp-contract=off: the greedy key is specified as a fixed
 // sequence of IEEE double operations so that any implementation of the same
@@ -249,6 +250,189 @@ std::vector<int32_t> slice_finder(const std::vector<IdSet>& leaves, const int32_
   return S;
 }
 
+// a - b for a >= b
+static BigSum big_sub(const BigSum& a, const BigSum& b) {
+  BigSum r = a;
+  uint64_t borrow = 0;
+  for (size_t i = 0; i < r.w.size(); ++i) {
+    uint64_t bi = i < b.w.size() ? b.w[i] : 0;
+    uint64_t d = r.w[i] - bi;
+    uint64_t b1 = r.w[i] < bi;
+    uint64_t d2 = d - borrow;
+    uint64_t b2 = d < borrow;
+    r.w[i] = d2;
+    borrow = b1 | b2;
+  }
+  while (!r.w.empty() && r.w.back() == 0) r.w.pop_back();
+  return r;
+}
+
+namespace {
+
+// Eq. (4) for a slicing set and its one-element variants. Each contraction
+// node keeps |S n s_v|; a variant that removes `out` (or nothing, -1) and
+// adds `in` (or nothing) changes it by membership only.
+struct SlicedCost {
+  const Tree& tree;
+  std::vector<IdSet> ns;    // s_v of every contraction node
+  std::vector<int> inter;   // |S n s_v| for the current S
+  int nS = 0;
+  explicit SlicedCost(const Tree& t) : tree(t) {
+    for (int32_t v = t.L; v < (int32_t)t.sets.size(); ++v) ns.push_back(t.node_set(v));
+    inter.assign(ns.size(), 0);
+  }
+  void reset(const std::vector<int32_t>& S) {
+    IdSet s(S.begin(), S.end());
+    std::sort(s.begin(), s.end());
+    nS = (int)s.size();
+    for (size_t v = 0; v < ns.size(); ++v) inter[v] = (int)set_and(ns[v], s).size();
+  }
+  BigSum variant(int32_t out, int32_t in) const {
+    BigSum c;
+    int n = nS - (out >= 0) + (in >= 0);
+    for (size_t v = 0; v < ns.size(); ++v) {
+      int k = inter[v];
+      if (out >= 0 && set_has(ns[v], out)) --k;
+      if (in >= 0 && set_has(ns[v], in)) ++k;
+      c.add_pow2((int)ns[v].size() + n - k);
+    }
+    return c;
+  }
+};
+
+int dim_after(const IdSet& s, const std::vector<char>& inS) {
+  int d = 0;
+  for (int32_t x : s) d += !inS[x];
+  return d;
+}
+
+}  // namespace
+
+std::vector<int32_t> slice_refine(const Tree& tree, int t, const std::vector<int32_t>& S0,
+                                  const RefineParams& p, RefineStats* st) {
+  int32_t max_id = -1;
+  for (auto& s : tree.sets)
+    for (int32_t x : s) max_id = std::max(max_id, x);
+  for (int32_t x : S0) max_id = std::max(max_id, x);
+  std::vector<char> inS(max_id + 1, 0);
+  for (int32_t x : S0) {
+    require(x >= 0 && !inS[x], "slicing set has a negative or repeated id");
+    inS[x] = 1;
+  }
+  for (auto& s : tree.sets)
+    require(dim_after(s, inS) <= t, "the slicing set does not meet the target rank", LTN_E_CAP);
+  require(p.n_fixed >= 0 && p.n_fixed <= (int)S0.size(), "n_fixed out of range");
+  require(p.iters_per_temp >= 1, "iters_per_temp must be >= 1");
+  require(p.alpha > 0.0 && p.alpha < 1.0, "alpha must be in (0, 1)");
+  require(p.tf > 0.0 && p.t0 > 0.0, "temperatures must be positive");
+  RefineStats stats;
+  std::vector<int32_t> cur = S0;
+  SlicedCost sc(tree);
+  sc.reset(cur);
+  BigSum cur_c = sc.variant(-1, -1);
+  std::vector<int32_t> best = cur;
+  BigSum best_c = cur_c;
+  double T = p.t0;
+  int64_t it = 0;
+  for (;;) {
+    for (int r = 0; r < p.iters_per_temp; ++r) {
+      const int free = (int)cur.size() - p.n_fixed;
+      if (free <= 0) break;
+      const double u = keyed_uniform(p.seed, (uint64_t)it, 0, 0);
+      const int slot = p.n_fixed + std::min((int)(u * free), free - 1);
+      const int32_t idx = cur[slot];
+      // Algorithm 3: critical tensors in the lifetime of idx
+      std::vector<int32_t> crit;
+      for (int32_t v = 0; v < (int32_t)tree.sets.size(); ++v)
+        if (set_has(tree.sets[v], idx) && dim_after(tree.sets[v], inS) == t) crit.push_back(v);
+      if (crit.empty()) {
+        inS[idx] = 0;
+        cur.erase(cur.begin() + slot);
+        sc.reset(cur);
+        cur_c = sc.variant(-1, -1);
+        ++stats.dropped;
+      } else {
+        // Algorithm 4: indices held by every critical tensor, not sliced
+        IdSet cand = tree.sets[crit[0]];
+        for (int32_t v : crit) cand = set_and(cand, tree.sets[v]);
+        IdSet c2;
+        for (int32_t x : cand)
+          if (!inS[x]) c2.push_back(x);
+        for (int32_t c : c2) {
+          const int32_t occupant = cur[slot];
+          BigSum new_c = sc.variant(occupant, c);
+          ++stats.proposals;
+          bool take;
+          if (new_c.compare(cur_c) < 0) {
+            take = true;
+          } else {
+            const double rel = big_sub(new_c, cur_c).to_double() / cur_c.to_double();
+            const double prob = std::exp(-rel / T);
+            take = keyed_uniform(p.seed, (uint64_t)it, 1, (uint64_t)c) < prob;
+          }
+          if (take) {
+            inS[occupant] = 0;
+            inS[c] = 1;
+            cur[slot] = c;
+            sc.reset(cur);
+            cur_c = new_c;
+            ++stats.accepted;
+          }
+          if (cur_c.compare(best_c) < 0) {
+            best = cur;
+            best_c = cur_c;
+          }
+        }
+      }
+      if (cur_c.compare(best_c) < 0) {
+        best = cur;
+        best_c = cur_c;
+      }
+      ++it;
+    }
+    stats.iterations = (int32_t)it;
+    T = T * p.alpha;
+    if (T < p.tf || (int)cur.size() <= p.n_fixed) break;
+  }
+  if (st) *st = stats;
+  return best;
+}
+
+std::vector<int32_t> slice_greedy_overhead(const Tree& tree, int t, const std::vector<int32_t>& pre) {
+  std::vector<int32_t> S = pre;
+  if (t < 0) return S;
+  int32_t max_id = -1;
+  for (auto& s : tree.sets)
+    for (int32_t x : s) max_id = std::max(max_id, x);
+  for (int32_t x : pre) max_id = std::max(max_id, x);
+  std::vector<char> inS(max_id + 1, 0);
+  for (int32_t x : pre) inS[x] = 1;
+  SlicedCost sc(tree);
+  for (;;) {
+    std::map<int32_t, int> count;  // ascending id
+    for (auto& s : tree.sets)
+      if (dim_after(s, inS) > t)
+        for (int32_t x : s)
+          if (!inS[x]) count[x]++;
+    if (count.empty()) return S;
+    sc.reset(S);
+    bool have = false;
+    BigSum bc;
+    int32_t pick = -1;
+    for (auto [x, n] : count) {
+      BigSum c = sc.variant(-1, x);
+      int cmp = have ? c.compare(bc) : -1;
+      if (!have || cmp < 0 || (cmp == 0 && n > count[pick])) {
+        have = true;
+        bc = c;
+        pick = x;
+      }
+    }
+    S.push_back(pick);
+    inS[pick] = 1;
+  }
+}
+
 }  // namespace ltn
 
 using namespace ltn;
@@ -359,5 +543,50 @@ extern "C" ltn_status ltn_path_search(const ltn_network* net, int32_t t, const i
     std::copy(bS.begin(), bS.end(), S_out);
     *n_sliced = (int32_t)bS.size();
     if (best_trial) *best_trial = btrial;
+  });
+}
+
+extern "C" ltn_status ltn_slice_refine(const ltn_network* net, const int32_t* path, int32_t t,
+                                       const int32_t* S_in, int32_t n_in,
+                                       const ltn_refine_opts* o, int32_t* S_out, int32_t* n_out,
+                                       ltn_refine_stats* stats) {
+  return guarded([&] {
+    Net n = Net::from_abi(net, false);
+    require(path && o && S_out && n_out, "NULL argument");
+    require(t >= 0, "the refiner needs a target rank t >= 0");
+    require(n_in >= 0 && (n_in == 0 || S_in), "bad slicing set");
+    Tree tr = Tree::build(n.sets, path);
+    RefineParams rp;
+    rp.t0 = o->t0;
+    rp.alpha = o->alpha;
+    rp.tf = o->tf;
+    rp.iters_per_temp = o->iters_per_temp;
+    rp.n_fixed = o->n_fixed;
+    rp.seed = o->seed;
+    RefineStats st;
+    auto S = slice_refine(tr, t, std::vector<int32_t>(S_in, S_in + n_in), rp, &st);
+    std::copy(S.begin(), S.end(), S_out);
+    *n_out = (int32_t)S.size();
+    if (stats) {
+      stats->iterations = st.iterations;
+      stats->proposals = st.proposals;
+      stats->accepted = st.accepted;
+      stats->dropped = st.dropped;
+    }
+  });
+}
+
+extern "C" ltn_status ltn_slice_greedy_overhead(const ltn_network* net, const int32_t* path,
+                                                int32_t t, const int32_t* pre, int32_t n_pre,
+                                                int32_t* S_out, int32_t cap, int32_t* n_sliced) {
+  return guarded([&] {
+    Net n = Net::from_abi(net, false);
+    require(path && S_out && n_sliced, "NULL argument");
+    require(n_pre >= 0 && (n_pre == 0 || pre), "bad pre list");
+    Tree tr = Tree::build(n.sets, path);
+    auto S = slice_greedy_overhead(tr, t, std::vector<int32_t>(pre, pre + n_pre));
+    require((int32_t)S.size() <= cap, "S_out too small", LTN_E_NOMEM);
+    std::copy(S.begin(), S.end(), S_out);
+    *n_sliced = (int32_t)S.size();
   });
 }

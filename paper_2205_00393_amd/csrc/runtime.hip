@@ -768,6 +768,22 @@ extern "C" ltn_status ltn_permute(const void* d_in, void* d_out, int32_t rank, c
       d.outer_src[k] = (int8_t)outer[k];
       d.outer_dst[k] = (int8_t)perm[outer[k]];
     }
+    // LDS swizzle: the tile bits read by one half-wave in destination order
+    // are dst_tile[0..4]; those at tile bit >= 5 each get a distinct low bit
+    // not already among them, so the 32 slots differ in their low 5 bits.
+    {
+      const int nr = std::min(d.n_tile, 5);
+      bool used[5] = {false, false, false, false, false};
+      for (int r = 0; r < nr; ++r)
+        if (d.dst_tile[r] < 5) used[d.dst_tile[r]] = true;
+      int next = 0;
+      for (int r = 0; r < nr; ++r)
+        if (d.dst_tile[r] >= 5) {
+          while (used[next]) ++next;
+          used[next] = true;
+          d.swz[d.dst_tile[r] - 5] = (uint8_t)(1u << next);
+        }
+    }
     launch_permute(reinterpret_cast<const float2*>(d_in), reinterpret_cast<float2*>(d_out), d,
                    reinterpret_cast<hipStream_t>(stream));
     check_launch();

@@ -183,6 +183,30 @@ def slice_finder(net: Network, path, t: int, pre: Sequence[int] = ()) -> List[in
     return list(out[: n.value])
 
 
+def slice_refine(net: Network, path, t: int, S: Sequence[int], n_fixed: int = 0, t0: float = 1.0,
+                 alpha: float = 0.98, tf: float = 1e-3, iters_per_temp: int = 1, seed: int = 0):
+    """Slice refiner (Algorithms 2-4); returns (S, stats dict)."""
+    o = L.RefineOpts(t0, alpha, tf, iters_per_temp, n_fixed, seed)
+    out = (C.c_int32 * max(1, len(S)))()
+    n = C.c_int32()
+    st = L.RefineStats()
+    L.check(L.lib().ltn_slice_refine(C.byref(net.view), _path_array(path), t, L.i32_array(list(S)),
+                                     len(S), C.byref(o), out, C.byref(n), C.byref(st)))
+    return list(out[: n.value]), {"iterations": st.iterations, "proposals": st.proposals,
+                                  "accepted": st.accepted, "dropped": st.dropped}
+
+
+def slice_greedy_overhead(net: Network, path, t: int, pre: Sequence[int] = ()) -> List[int]:
+    """Greedy least-overhead slicer (comparison baseline for Algorithm 1)."""
+    cap = net.n_indices + 1
+    out = (C.c_int32 * cap)()
+    n = C.c_int32()
+    L.check(L.lib().ltn_slice_greedy_overhead(C.byref(net.view), _path_array(path), t,
+                                              L.i32_array(list(pre)), len(pre), out, cap,
+                                              C.byref(n)))
+    return list(out[: n.value])
+
+
 def path_search(net: Network, t: int, pre: Sequence[int] = (), alphas=(1.0,), taus=(0.0,),
                 n_seeds: int = 1, seed_base: int = 0):
     """Randomised greedy trials + slice finder; returns (path, S, best trial)."""

@@ -179,3 +179,48 @@ def test_arena_liveness_no_overlap(name):
                 lo = max(off[u], off[v])
                 hi = min(off[u] + (8 << rank[u]), off[v] + (8 << rank[v]))
                 assert lo >= hi, f"tensors {u} and {v} overlap while both alive"
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_slice_refiner_and_greedy_slicer_bit_exact_random(seed):
+    idx, n, opens = random_network(seed, 10, 16, 2)
+    data = [np.ones([2] * len(ix), dtype=np.complex64) for ix in idx]
+    cnet = P.Network.from_arrays(idx, data, opens, n)
+    p = opl.greedy_path(idx, 1.0, 0.0, seed)
+    tree = opl.Tree(idx, p)
+    mx = max(len(s) for s in tree.sets)
+    for t in range(max(1, mx - 4), mx):
+        S = opl.slice_finder(tree, t)
+        for kw in ({"seed": seed}, {"seed": seed + 100, "iters_per_temp": 3, "alpha": 0.9},
+                   {"seed": seed, "n_fixed": min(1, len(S)), "t0": 0.05, "tf": 1e-2}):
+            assert P.slice_refine(cnet, p, t, S, **kw) == opl.slice_refine(tree, t, S, **kw)
+        assert P.slice_greedy_overhead(cnet, p, t) == opl.greedy_overhead_slicer(tree, t)
+        assert P.slice_greedy_overhead(cnet, p, t, S[:1]) == opl.greedy_overhead_slicer(tree, t, S[:1])
+
+
+@pytest.mark.parametrize("name,t,kw", [("rqc12", 6, {}), ("rqc30", 22, {"tf": 0.05}),
+                                       ("rqc20_grad", 10, {"tf": 0.05})])
+def test_slice_refiner_bit_exact_workloads(name, t, kw):
+    w, onet, cnet = _both(name)
+    pre = list(reversed(onet.open_ids)) if w.slice_open else []
+    p = opl.greedy_path(onet.indices, 0.5, 0.3, 1, exclude=pre)
+    tree = opl.Tree(onet.indices, p)
+    S = opl.slice_finder(tree, t, pre)
+    got = P.slice_refine(cnet, p, t, S, n_fixed=len(pre), **kw)
+    want = opl.slice_refine(tree, t, S, n_fixed=len(pre), **kw)
+    assert got == want
+    assert got[0][: len(pre)] == pre
+    assert tree.sliced_cost(got[0]) <= tree.sliced_cost(S)
+
+
+def test_slice_refiner_errors():
+    idx, n, opens = random_network(0, 8, 12, 2)
+    data = [np.ones([2] * len(ix), dtype=np.complex64) for ix in idx]
+    cnet = P.Network.from_arrays(idx, data, opens, n)
+    p = opl.greedy_path(idx, 1.0, 0.0, 0)
+    with pytest.raises(P.LtnError, match="target rank"):
+        P.slice_refine(cnet, p, 1, [])
+    with pytest.raises(P.LtnError, match="alpha"):
+        P.slice_refine(cnet, p, 99, [], alpha=1.5)
+    with pytest.raises(P.LtnError, match="repeated"):
+        P.slice_refine(cnet, p, 99, [0, 0])
