@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--workload", default="rqc30", choices=["rqc30", "rqc53"],
                     help="rqc30: every slice per step; rqc53: a seeded sample of --slices slices")
     ap.add_argument("--slices", type=int, default=8, help="rqc53: sampled slices per step")
+    ap.add_argument("--path-variant", default="c64,split_bf16",
+                    help="modes to time on the reconfigured path as well ('' to skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -103,85 +105,124 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from workload import sample_slice_ids
     w = make_workload(args.workload)
-    t0 = time.perf_counter()
-    pr = P.prepare(w)
-    plan = pr.plan()
-    costs = P.tree_costs(pr.net, pr.path, pr.sliced)
-    t_plan = time.perf_counter() - t0
-    if args.workload == "rqc30":
-        n_slices = 1 << len(pr.sliced)
-        ids = None
-    else:
-        # the seeded subset of 2^10 slice ids, first --slices of them
-        ids = sample_slice_ids(len(pr.sliced), 1024, 3)[: args.slices]
-        n_slices = len(ids)
-    info = plan.info()
-    macs_slice = info["macs_per_slice"]
-    flops_step = 8.0 * macs_slice * n_slices
-    steps = plan.steps()
-    log(f"planned in {t_plan:.2f}s: |S|={len(pr.sliced)} C(B,S)=2^{costs.log2_sliced:.2f} "
-        f"overhead={costs.overhead:.4f} per-slice MACs={macs_slice:.3e}")
-
-    batch = plan.bind(batch=n_slices) if plan.workspace_size(n_slices) < 0.7 * torch.cuda.mem_get_info()[0] \
-        else plan.bind()
-
-    def run_step(out, mode):
-        if ids is None:
-            plan.execute_range(0, n_slices, out, mode)
-        else:
-            plan.execute(ids, out, mode)
-    log(f"bound: batch={batch}, workspace={plan.workspace_size(batch) / 2**30:.2f} GiB")
     ref = np.load(GOLDEN) if os.path.exists(GOLDEN) else None
 
-    def measure(mode):
+    def run_plan(pr, mode_list, tag):
+        """Bind a prepared plan and time each mode on it; returns (results,
+        plan facts)."""
         t0 = time.perf_counter()
-        cache = args.tune_cache  # one file for all modes (keys carry the mode)
-        plan.autotune(mode, cache)
-        log(f"[{mode}] autotuned in {time.perf_counter() - t0:.2f}s")
-        out = plan.new_output()
-        for _ in range(args.warmup):
-            out.zero_()
-            run_step(out, mode)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            out.zero_()
-            run_step(out, mode)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        res = {"tflops": flops_step * args.steps / dt / 1e12, "ms_per_step": 1e3 * dt / args.steps,
-               "sec_per_slice": dt / args.steps / n_slices}
-        if ref is not None and args.workload == "rqc30":
-            got = out.cpu().numpy()
-            res["rel_l2_error"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-        # the dominant kernel (the MFMA complex GEMM): live per-step HIP
-        # events on the plan's stream (a replay of one batch outside the graph)
-        ms = np.zeros(len(steps))
-        reps = 3
-        for _ in range(reps):
-            ms += plan.profile_steps(0 if ids is None else int(ids[0]), mode)
-        ms /= reps
-        mf_flops, mf_ms, mf_launch, split_flops = 0.0, 0.0, 0, 0.0
-        for k, st in enumerate(steps):
-            kind, _, _, _ = plan.step_kernel(k, mode)
-            if kind > 0:
-                f = 8.0 * (1 << (st["m"] + st["k"] + st["n"])) * batch
-                mf_flops += f
-                mf_ms += ms[k]
-                mf_launch += 1
-                if kind == 2:
-                    split_flops += f
-        res["mfma_ms_per_batch"] = mf_ms
-        res["step_ms_per_batch"] = float(ms.sum())
-        res["mfma_launches_per_batch"] = mf_launch
-        res["mfma_tflops"] = mf_flops / (mf_ms * 1e-3) / 1e12 if mf_ms > 0 else 0.0
-        res["split_mac_fraction"] = split_flops / (8.0 * macs_slice * batch)
-        log(f"[{mode}] {res['ms_per_step']:.2f} ms/step, {res['tflops']:.2f} TFLOP/s, "
-            f"MFMA {mf_ms:.2f} of {res['step_ms_per_batch']:.2f} ms per batch "
-            f"({res['mfma_tflops']:.2f} TFLOP/s), err {res.get('rel_l2_error')}")
-        return res
+        plan = pr.plan()
+        costs = P.tree_costs(pr.net, pr.path, pr.sliced)
+        t_plan = time.perf_counter() - t0 + pr_seconds[tag]
+        if args.workload == "rqc30":
+            n_slices = 1 << len(pr.sliced)
+            ids = None
+        else:
+            # the seeded subset of 2^10 slice ids, first --slices of them
+            ids = sample_slice_ids(len(pr.sliced), 1024, 3)[: args.slices]
+            n_slices = len(ids)
+        info = plan.info()
+        macs_slice = info["macs_per_slice"]
+        flops_step = 8.0 * macs_slice * n_slices
+        steps = plan.steps()
+        log(f"[{tag}] planned in {t_plan:.2f}s: |S|={len(pr.sliced)} C(B,S)=2^{costs.log2_sliced:.2f} "
+            f"overhead={costs.overhead:.4f} per-slice MACs={macs_slice:.3e}")
+        batch = plan.bind(batch=n_slices) if plan.workspace_size(n_slices) < 0.7 * torch.cuda.mem_get_info()[0] \
+            else plan.bind()
+        log(f"[{tag}] bound: batch={batch}, workspace={plan.workspace_size(batch) / 2**30:.2f} GiB")
 
-    results = {m: measure(m) for m in args.modes.split(",")}
+        def run_step(out, mode):
+            if ids is None:
+                plan.execute_range(0, n_slices, out, mode)
+            else:
+                plan.execute(ids, out, mode)
+
+        def measure(mode):
+            t0 = time.perf_counter()
+            cache = args.tune_cache  # one file for all modes (keys carry the mode)
+            plan.autotune(mode, cache)
+            log(f"[{tag}/{mode}] autotuned in {time.perf_counter() - t0:.2f}s")
+            out = plan.new_output()
+            for _ in range(args.warmup):
+                out.zero_()
+                run_step(out, mode)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                out.zero_()
+                run_step(out, mode)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res = {"tflops": flops_step * args.steps / dt / 1e12, "ms_per_step": 1e3 * dt / args.steps,
+                   "sec_per_slice": dt / args.steps / n_slices}
+            if ref is not None and args.workload == "rqc30":
+                got = out.cpu().numpy()
+                res["rel_l2_error"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            # the dominant kernel (the MFMA complex GEMM): live per-step HIP
+            # events on the plan's stream (a replay of one batch outside the graph)
+            ms = np.zeros(len(steps))
+            reps = 3
+            for _ in range(reps):
+                ms += plan.profile_steps(0 if ids is None else int(ids[0]), mode)
+            ms /= reps
+            mf_flops, mf_ms, mf_launch, split_flops = 0.0, 0.0, 0, 0.0
+            for k, st in enumerate(steps):
+                kind, _, _, _ = plan.step_kernel(k, mode)
+                if kind in (1, 2):
+                    f = 8.0 * (1 << (st["m"] + st["k"] + st["n"])) * batch
+                    mf_flops += f
+                    mf_ms += ms[k]
+                    mf_launch += 1
+                    if kind == 2:
+                        split_flops += f
+            res["mfma_ms_per_batch"] = mf_ms
+            res["step_ms_per_batch"] = float(ms.sum())
+            res["mfma_launches_per_batch"] = mf_launch
+            res["mfma_tflops"] = mf_flops / (mf_ms * 1e-3) / 1e12 if mf_ms > 0 else 0.0
+            res["split_mac_fraction"] = split_flops / (8.0 * macs_slice * batch)
+            log(f"[{tag}/{mode}] {res['ms_per_step']:.2f} ms/step, {res['tflops']:.2f} TFLOP/s, "
+                f"MFMA {mf_ms:.2f} of {res['step_ms_per_batch']:.2f} ms per batch "
+                f"({res['mfma_tflops']:.2f} TFLOP/s), err {res.get('rel_l2_error')}")
+            return res
+
+        results = {m: measure(m) for m in mode_list}
+        facts = dict(n_slices=n_slices, batch=batch, costs=costs, macs_slice=macs_slice,
+                     flops_step=flops_step, n_sliced=len(pr.sliced), plan_seconds=t_plan)
+        del plan
+        torch.cuda.empty_cache()
+        return results, facts
+
+    pr_seconds = {}
+    t0 = time.perf_counter()
+    pr = P.prepare(w)
+    pr_seconds["greedy"] = time.perf_counter() - t0
+    results, facts = run_plan(pr, args.modes.split(","), "greedy")
+    n_slices, batch, costs = facts["n_slices"], facts["batch"], facts["costs"]
+    macs_slice, flops_step = facts["macs_slice"], facts["flops_step"]
+
+    # the same workload on a better path: greedy trials improved by subtree
+    # reconfiguration (and, for the 53-qubit case, a refined slicing set)
+    variant = None
+    if args.path_variant:
+        t0 = time.perf_counter()
+        prv = P.prepare(w, reconf_k=8, refine_seeds=2 if args.workload == "rqc53" else 0)
+        pr_seconds["reconf"] = time.perf_counter() - t0
+        vres, vf = run_plan(prv, args.path_variant.split(","), "reconf")
+        variant = {"path": "randomised greedy + subtree reconfiguration (k=8)" +
+                   (" + slice refiner" if args.workload == "rqc53" else ""),
+                   "plan_seconds": round(vf["plan_seconds"], 3),
+                   "sliced_indices": vf["n_sliced"], "log2_C_BS": round(vf["costs"].log2_sliced, 4),
+                   "overhead": round(vf["costs"].overhead, 5), "macs_per_slice": vf["macs_slice"],
+                   "projected_seconds_all_slices": {m: r["sec_per_slice"] * 2.0 ** vf["n_sliced"]
+                                                    for m, r in vres.items()},
+                   "modes": {m: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
+                             for m, r in vres.items()}}
+        for m, r in vres.items():
+            if m in results:
+                variant["modes"][m]["time_to_solution_speedup_vs_greedy_path"] = round(
+                    (results[m]["sec_per_slice"] * 2.0 ** len(pr.sliced)) /
+                    (r["sec_per_slice"] * 2.0 ** vf["n_sliced"]), 3)
+
     main_mode = args.modes.split(",")[0]
     r0 = results[main_mode]
     tflops, ms_step, err = r0["tflops"], r0["ms_per_step"], r0.get("rel_l2_error")
@@ -237,6 +278,7 @@ def main():
         "modes": modes,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "path_variant": variant,
     }
     print(json.dumps(line), flush=True)
 

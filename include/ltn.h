@@ -183,7 +183,11 @@ ltn_status ltn_slice_finder(const ltn_network* net, const int32_t* path, int32_t
 /* Randomised greedy search: for every (alpha, tau, seed) trial below, run
  * ltn_greedy_path then ltn_slice_finder, and keep the trial with the
  * smallest (C(B,S), |S|, trial number). Trials are numbered alpha-major,
- * then tau, then seed (0..n_seeds-1); trials with tau = 0 use seed 0 only. */
+ * then tau, then seed (0..n_seeds-1); trials with tau = 0 use seed 0 only.
+ * With reconf_k >= 3 every trial's path is improved before and after the
+ * slice finder by ltn_tree_reconfigure (k = reconf_k, reconf_sweeps sweeps;
+ * first with S = pre and no cap, then with the trial's S under the cap t).
+ * reconf_k = 0 leaves the greedy paths as they are. */
 typedef struct ltn_search_opts {
   int32_t n_alpha;
   const double* alphas;
@@ -191,6 +195,8 @@ typedef struct ltn_search_opts {
   const double* taus;
   int32_t n_seeds;
   uint64_t seed_base;
+  int32_t reconf_k;
+  int32_t reconf_sweeps;
 } ltn_search_opts;
 ltn_status ltn_path_search(const ltn_network* net, int32_t t, const int32_t* pre, int32_t n_pre,
                            const ltn_search_opts* opts, int32_t* path_out, int32_t* S_out,
@@ -229,6 +235,24 @@ typedef struct ltn_refine_stats {
 ltn_status ltn_slice_refine(const ltn_network* net, const int32_t* path, int32_t t,
                             const int32_t* S_in, int32_t n_in, const ltn_refine_opts* opts,
                             int32_t* S_out, int32_t* n_out, ltn_refine_stats* stats);
+
+/* Subtree reconfiguration of a contraction tree (a path improvement in the
+ * spirit of the local tuning of the tree between slicing steps named in
+ * Sec. 2.2). Each sweep visits every contraction node v in SSA order: a
+ * frontier grows from v by replacing the frontier node with the largest
+ * node set (Eq. 1's s_v without the indices in S; ties: smaller id) by its
+ * two children, up to k tensors (k in 2..16); the frontier is re-contracted
+ * in the order of least summed node cost 2^|s_v - S| found by exhaustive
+ * search over its subsets (with t >= 0, no intermediate tensor may exceed
+ * rank t after S; t < 0: no cap), and the new subtree is kept when strictly
+ * cheaper. Costs saturate at 2^120. After each sweep the tree is written
+ * out again as an SSA path in post order (left child first); sweeps stop
+ * early when one changes nothing. path_out: 2 (n_leaves - 1) ids, may not
+ * alias path. With S empty this lowers Eq. (1); with S and t it lowers
+ * Eq. (4) while every tensor stays within the cap. */
+ltn_status ltn_tree_reconfigure(const ltn_network* net, const int32_t* path, int32_t k,
+                                int32_t sweeps, const int32_t* S, int32_t n_sliced, int32_t t,
+                                int32_t* path_out);
 
 /* Greedy least-overhead slicer, the strategy the paper attributes to
  * cotengra (Sec. 2.2), for comparison with Algorithm 1: starting from pre,
@@ -361,9 +385,19 @@ ltn_status ltn_permute(const void* d_in, void* d_out, int32_t rank, const int32_
 
 /* Kernel chosen for a step in a mode after ltn_bind / ltn_autotune:
  * kind 0 = generic VALU kernel (tk threads per output), 1 = complex64 MFMA
- * GEMM, 2 = split-precision MFMA GEMM; cfg = tile configuration of that
- * kind (-1 for the generic kernel); swap = operands exchanged on the MFMA
- * (its rows come from B). Requires a bound plan. */
+ * GEMM, 2 = split-precision MFMA GEMM, 3 = narrow-step kernel (k + n <= 10,
+ * n <= 6: A tile in LDS, B broadcast from LDS, outputs staged in address
+ * order); cfg = tile configuration of that kind (-1 for the generic
+ * kernel); swap = operands exchanged (rows come from B). Requires a bound
+ * plan. */
+/* Force the kernel of one step in one mode (same encoding as
+ * ltn_step_kernel; tk in {1, 8, 64} for kind 0). Errors: LTN_E_INVALID if
+ * the kernel does not fit the step (tile too large, narrow limits) or a
+ * split kind is asked for in complex64 mode; LTN_E_STATE if unbound. The
+ * plan's captured graphs are dropped. */
+ltn_status ltn_set_step_kernel(ltn_plan* plan, int32_t step, int32_t mode, int32_t kind,
+                               int32_t cfg, int32_t swap, int32_t tk);
+
 ltn_status ltn_step_kernel(const ltn_plan* plan, int32_t step, int32_t mode, int32_t* kind,
                            int32_t* cfg, int32_t* swap, int32_t* tk);
 

@@ -51,6 +51,20 @@ silent:
   with u = keyed_uniform(seed, i, 0, 0); candidate c is accepted uphill
   when keyed_uniform(seed, i, 1, c) < p.
 
+Subtree reconfiguration (a path improvement in the spirit of the local
+tuning of the contraction tree cited in Sec. 2.2; the paper takes its
+paths from cotengra instead): for every contraction node v in SSA order,
+grow a frontier from v by repeatedly replacing the frontier node with the
+largest node set (after removing S; ties: smaller id) by its two children,
+up to k tensors; re-contract the frontier in the order of least summed node
+cost 2^|s_v - S| (exhaustive over subsets; with a target t, intermediate
+tensors above t after S are not allowed); keep the new subtree when it is
+strictly cheaper. Costs saturate at 2^120 (no finite tree reaches it).
+Ties in the subset search keep the first minimum when the split's smaller
+part (as a bit mask over the frontier) runs downward. New nodes reuse the
+subtree's ids; after every sweep the tree is written out again as an SSA
+path in post order (left child first).
+
 Greedy-overhead slicer (the strategy attributed to cotengra in Sec. 2.2):
 while some tensor is above t, slice the index, among those of tensors above
 t, whose addition gives the smallest C(B,S); ties: held by the most
@@ -272,18 +286,25 @@ def slice_finder(tree: Tree, t: int, pre: Sequence[int] = (),
 
 
 def path_search(leaf_indices, t: int, pre: Sequence[int] = (), alphas=(1.0,), taus=(0.0,),
-                n_seeds: int = 1, seed_base: int = 0):
+                n_seeds: int = 1, seed_base: int = 0, reconf_k: int = 0, reconf_sweeps: int = 4):
     """Randomised greedy trials (alpha-major, then tau, then seed; tau = 0
     runs seed 0 only), each followed by the slice finder; keep the smallest
-    (C(B,S), |S|, trial number). Returns (path, S, trial)."""
+    (C(B,S), |S|, trial number). Returns (path, S, trial). With reconf_k >= 3
+    each trial's path goes through ``reconfigure`` before the slice finder
+    (S = pre, no cap) and after it (the trial's S, cap t)."""
     best = None
     trial = 0
     for alpha in alphas:
         for tau in taus:
             for sd in range(n_seeds if tau > 0.0 else 1):
                 p = greedy_path(leaf_indices, alpha, tau, seed_base + sd, exclude=pre)
+                if reconf_k >= 3:
+                    p = reconfigure(leaf_indices, p, reconf_k, reconf_sweeps, pre, -1)
                 tr = Tree(leaf_indices, p)
                 S = slice_finder(tr, t, pre)
+                if reconf_k >= 3 and t >= 0:
+                    p = reconfigure(leaf_indices, p, reconf_k, reconf_sweeps, S, t)
+                    tr = Tree(leaf_indices, p)
                 key = (tr.sliced_cost(S), len(S), trial)
                 if best is None or key < best[0]:
                     best = (key, p, S, trial)
@@ -382,3 +403,130 @@ def greedy_overhead_slicer(tree: Tree, t: int, pre: Sequence[int] = ()) -> List[
                 count[x] = count.get(x, 0) + 1
         pick = min(count, key=lambda x: (tree.sliced_cost(S + [x]), -count[x], x))
         S.append(pick)
+
+
+SAT = 1 << 120
+
+
+def _sat(x: int) -> int:
+    return x if x < SAT else SAT
+
+
+def reconfigure(leaf_indices: Sequence[Sequence[int]], path: Sequence[Tuple[int, int]], k: int,
+                sweeps: int = 1, S: Sequence[int] = (), t: int = -1) -> List[Tuple[int, int]]:
+    """Subtree reconfiguration; returns the new SSA path (same leaves)."""
+    Sset = frozenset(S)
+    L = len(leaf_indices)
+    sets: List[frozenset] = [frozenset(ix) for ix in leaf_indices]
+    kids: List[Optional[Tuple[int, int]]] = [None] * L
+    for a, b in path:
+        sets.append(sets[a] ^ sets[b])
+        kids.append((a, b))
+    n = len(sets)
+
+    def node_cost(sa, sb):
+        return _sat(1 << len((sa | sb) - Sset)) if len((sa | sb) - Sset) < 120 else SAT
+
+    for _ in range(sweeps):
+        improved = False
+        for v in range(L, n):
+            front = [v]
+            while len(front) < k:
+                inner = [u for u in front if kids[u] is not None]
+                if not inner:
+                    break
+                u = max(inner, key=lambda u: (len((sets[kids[u][0]] | sets[kids[u][1]]) - Sset), -u))
+                front.remove(u)
+                front.extend(kids[u])
+            m = len(front)
+            if m < 3:
+                continue
+            inner_nodes: List[int] = []
+
+            def collect(u):
+                if u in front:
+                    return
+                inner_nodes.append(u)
+                collect(kids[u][0])
+                collect(kids[u][1])
+
+            collect(v)
+            old = 0
+            for u in inner_nodes:
+                old = _sat(old + node_cost(sets[kids[u][0]], sets[kids[u][1]]))
+            if old >= SAT:
+                continue
+            # exhaustive search over subsets of the frontier
+            tens = [frozenset()] * (1 << m)
+            for M in range(1, 1 << m):
+                low = M & -M
+                tens[M] = tens[M ^ low] ^ sets[front[low.bit_length() - 1]]
+            best = [0] * (1 << m)
+            choice = [0] * (1 << m)
+            full = (1 << m) - 1
+            for M in range(1, 1 << m):
+                if M & (M - 1) == 0:
+                    continue
+                if t >= 0 and M != full and len(tens[M] - Sset) > t:
+                    best[M] = SAT
+                    continue
+                bc, bsub = None, 0
+                sub = (M - 1) & M
+                while sub:
+                    o = M ^ sub
+                    if sub < o:
+                        c = _sat(_sat(best[sub] + best[o]) + node_cost(tens[sub], tens[o]))
+                        if bc is None or c < bc:
+                            bc, bsub = c, sub
+                    sub = (sub - 1) & M
+                best[M] = bc
+                choice[M] = bsub
+            if best[full] >= old:
+                continue
+            improved = True
+
+            def nest(M):
+                if M & (M - 1) == 0:
+                    return front[M.bit_length() - 1]
+                return (nest(choice[M]), nest(M ^ choice[M]))
+
+            pool = [u for u in inner_nodes if u != v]
+
+            def assign(tr, is_root):
+                if not isinstance(tr, tuple):
+                    return tr
+                a = assign(tr[0], False)
+                b = assign(tr[1], False)
+                u = v if is_root else pool.pop()
+                kids[u] = (a, b)
+                sets[u] = sets[a] ^ sets[b]
+                return u
+
+            assign(nest(full), True)
+        # write the tree out again in post order
+        order: List[int] = []
+        stack = [(n - 1, False)]
+        while stack:
+            u, done = stack.pop()
+            if kids[u] is None:
+                continue
+            if done:
+                order.append(u)
+            else:
+                stack.append((u, True))
+                stack.append((kids[u][1], False))
+                stack.append((kids[u][0], False))
+        newid = list(range(L)) + [0] * (n - L)
+        new_path = []
+        for u in order:
+            a, b = kids[u]
+            newid[u] = L + len(new_path)
+            new_path.append((newid[a], newid[b]))
+        sets = sets[:L]
+        kids = kids[:L]
+        for a, b in new_path:
+            sets.append(sets[a] ^ sets[b])
+            kids.append((a, b))
+        if not improved:
+            break
+    return [kids[u] for u in range(L, n)]

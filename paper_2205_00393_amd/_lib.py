@@ -40,7 +40,8 @@ class Costs(C.Structure):
 class SearchOpts(C.Structure):
     _fields_ = [("n_alpha", C.c_int32), ("alphas", C.POINTER(C.c_double)),
                 ("n_tau", C.c_int32), ("taus", C.POINTER(C.c_double)),
-                ("n_seeds", C.c_int32), ("seed_base", C.c_uint64)]
+                ("n_seeds", C.c_int32), ("seed_base", C.c_uint64), ("reconf_k", C.c_int32),
+                ("reconf_sweeps", C.c_int32)]
 
 
 class RefineOpts(C.Structure):
@@ -94,6 +95,7 @@ SIGNATURES = {
     "ltn_slice_refine": [C.POINTER(Network), I32P, I32, I32P, I32, C.POINTER(RefineOpts), I32P,
                          I32P, C.POINTER(RefineStats)],
     "ltn_slice_greedy_overhead": [C.POINTER(Network), I32P, I32, I32P, I32, I32P, I32, I32P],
+    "ltn_tree_reconfigure": [C.POINTER(Network), I32P, I32, I32, I32P, I32, I32, I32P],
     "ltn_plan_load": [C.POINTER(Network), I32P, I32, I32P, C.POINTER(Options), C.POINTER(P)],
     "ltn_plan_describe": [P, C.POINTER(PlanInfo)],
     "ltn_plan_step": [P, I32, C.POINTER(StepInfo)],
@@ -105,6 +107,7 @@ SIGNATURES = {
     "ltn_execute_grad": [P, U64P, U64, I32, P, P, P],
     "ltn_autotune": [P, I32, C.c_char_p],
     "ltn_profile_steps": [P, U64, I32, C.POINTER(C.c_float)],
+    "ltn_set_step_kernel": [P, I32, I32, I32, I32, I32, I32],
     "ltn_step_kernel": [P, I32, I32, I32P, I32P, I32P, I32P],
     "ltn_permute": [P, P, I32, I32P, C.c_int64, P],
     "ltn_plan_free": [P],

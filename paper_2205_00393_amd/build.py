@@ -35,6 +35,7 @@ SOURCES = [
     ("k_misc.hip", "hip"),
     ("k_mfma.hip", "hip"),
     ("k_permute.hip", "hip"),
+    ("k_narrow.hip", "hip"),
 ]
 
 

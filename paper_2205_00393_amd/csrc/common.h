@@ -123,6 +123,8 @@ struct RefineStats {
 };
 std::vector<int32_t> slice_refine(const Tree& tree, int t, const std::vector<int32_t>& S,
                                   const RefineParams& p, RefineStats* st);
+std::vector<int32_t> reconfigure(const std::vector<IdSet>& leaves, const std::vector<int32_t>& path,
+                                 int k, int sweeps, const IdSet& S, int t);
 std::vector<int32_t> slice_greedy_overhead(const Tree& tree, int t, const std::vector<int32_t>& pre);
 
 }  // namespace ltn

@@ -1,0 +1,191 @@
+// Narrow contraction steps: C[merge(m, n)] = sum_k A[m][k] B[n][k] with
+// small k and n (k + n <= 10, n <= 6) and many rows m, as in the stem steps that
+// absorb a small tensor. Such a step is bound by HBM (it reads A once and
+// writes C once, about (K N / (K + N)) / 2 complex MACs per 8 bytes), so
+// the kernel is built around coalesced traffic:
+//  * a tile of TM = 2^q consecutive rows of A is one contiguous chunk
+//    (rows are 2^k contiguous elements); it is loaded with consecutive
+//    lanes on consecutive addresses into LDS (row stride K + 1 elements, so
+//    that lanes reading the same k of consecutive rows hit distinct banks);
+//  * B (2^n x 2^k elements, <= 8 KiB) sits in LDS and is read by broadcast;
+//  * each thread computes NCH outputs of one row, keeping the A element in
+//    a register across them; results are staged in LDS in output-address
+//    order and written out with consecutive lanes on consecutive addresses
+//    where C's layout allows (tile output bits = the q lowest m positions
+//    and all n positions of C).
+// Tile-local maps are linear in the bits, so they are tables over 6-bit
+// halves (built per block). Optional per-slice max recording of |re|, |im|
+// for split-fp16 consumers, one atomic per wave.
+#include "kernels.h"
+
+namespace ltn {
+
+namespace {
+
+__device__ __forceinline__ uint64_t pdep_n(uint64_t x, uint64_t mask) {
+  uint64_t r = 0;
+  for (uint64_t bit = 1; mask; bit <<= 1) {
+    uint64_t low = mask & (~mask + 1);
+    if (x & bit) r |= low;
+    mask ^= low;
+  }
+  return r;
+}
+
+// LDS: A tile (TM * KP elements, also the staging area of the TM * N
+// outputs) then B (N * K elements); sized per launch.
+template <int NCH>
+__global__ __launch_bounds__(256) void k_narrow(NarrowDesc d) {
+  extern __shared__ float2 lds[];
+  float2* As = lds;
+  float2* Bs = lds + d.a_elems;
+  __shared__ uint64_t tT_lo[64], tT_hi[64];
+  __shared__ uint16_t tR_lo[64], tR_hi[64], tN[64];
+  const int tid = threadIdx.x;
+  const int q = d.q, K = 1 << d.k, N = 1 << d.n, TM = 1 << q;
+  const int KP = K == 1 ? 1 : K + 1;
+  const int NC = N / NCH;
+  const int items = TM * NC;
+  const int outs = TM * N;
+  const int tile_elems = TM * K;
+  for (int e = tid; e < 64; e += blockDim.x) {
+    tT_lo[e] = pdep_n((uint64_t)e, d.tmask);
+    tT_hi[e] = pdep_n((uint64_t)e << 6, d.tmask);
+    tR_lo[e] = (uint16_t)pdep_n((uint64_t)e, d.rt);
+    tR_hi[e] = (uint16_t)pdep_n((uint64_t)e << 6, d.rt);
+    tN[e] = (uint16_t)pdep_n((uint64_t)e, d.nt);
+  }
+  __syncthreads();
+  const int64_t tiles = int64_t(1) << (d.m - q);
+  const int64_t work = tiles * d.nb;
+  for (int64_t it = blockIdx.x; it < work; it += gridDim.x) {
+    const int64_t b = it / tiles, tile = it % tiles;
+    const uint64_t m0 = (uint64_t)tile << q;
+    const float2* Ab = d.A + b * d.sA + (int64_t)(m0 << d.k);
+    const float2* Bb = d.B + b * d.sB;
+    float2* Cb = d.C + b * d.sC + pdep_n(m0, d.cmask);
+    for (int e = tid; e < N * K; e += 256) Bs[e] = Bb[e];
+    if (K >= 2) {
+      // two elements of one row per 16-byte load
+      const float4* A4 = reinterpret_cast<const float4*>(Ab);
+      for (int e2 = tid; e2 < tile_elems / 2; e2 += 256) {
+        const float4 v = A4[e2];
+        const int e = 2 * e2, at = (e >> d.k) * KP + (e & (K - 1));
+        As[at] = make_float2(v.x, v.y);
+        As[at + 1] = make_float2(v.z, v.w);
+      }
+    } else {
+      for (int e = tid; e < tile_elems; e += 256) As[e] = Ab[e];
+    }
+    __syncthreads();
+    float2 acc[8];
+#pragma unroll
+    for (int i = 0; i < 8 / NCH; ++i) {
+      const int w = tid + 256 * i;
+#pragma unroll
+      for (int j = 0; j < NCH; ++j) acc[i * NCH + j] = make_float2(0.f, 0.f);
+      if (w < items) {
+        const int r = w & (TM - 1), nc = w >> q;
+        const float2* arow = As + r * KP;
+        const float2* bcol = Bs + nc * NCH * K;
+        for (int kk = 0; kk < K; ++kk) {
+          const float2 a = arow[kk];
+#pragma unroll
+          for (int j = 0; j < NCH; ++j) {
+            const float2 bv = bcol[j * K + kk];
+            acc[i * NCH + j].x += a.x * bv.x - a.y * bv.y;
+            acc[i * NCH + j].y += a.x * bv.y + a.y * bv.x;
+          }
+        }
+      }
+    }
+    __syncthreads();  // A tile no longer read: stage the outputs over it
+    float vmax = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8 / NCH; ++i) {
+      const int w = tid + 256 * i;
+      if (w < items) {
+        const int r = w & (TM - 1), nc = w >> q;
+        const int tr = tR_lo[r & 63] | tR_hi[r >> 6];
+#pragma unroll
+        for (int j = 0; j < NCH; ++j) {
+          const float2 v = acc[i * NCH + j];
+          As[tr | tN[nc * NCH + j]] = v;
+          vmax = fmaxf(vmax, fmaxf(fabsf(v.x), fabsf(v.y)));
+        }
+      }
+    }
+    __syncthreads();
+    if ((d.tmask & 1) && outs >= 2) {
+      // tile bit 0 is C's bit 0: outputs 2j and 2j + 1 are neighbours in C
+      for (int t2 = tid; t2 < outs / 2; t2 += 256) {
+        const int t = 2 * t2;
+        const float2 v0 = As[t], v1 = As[t + 1];
+        *reinterpret_cast<float4*>(Cb + (tT_lo[t & 63] | tT_hi[t >> 6])) = make_float4(v0.x, v0.y, v1.x, v1.y);
+      }
+    } else {
+      for (int t = tid; t < outs; t += 256) Cb[tT_lo[t & 63] | tT_hi[t >> 6]] = As[t];
+    }
+    if (d.scale_c) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off, 64));
+      if ((tid & 63) == 0 && vmax > 0.f) atomicMax(d.scale_c + b, __float_as_uint(vmax));
+    }
+    __syncthreads();  // the next tile overwrites As and Bs
+  }
+}
+
+}  // namespace
+
+bool narrow_fits(int m, int k, int n) { return k + n <= 10 && n <= 6 && m >= 0 && m <= 40; }
+
+void launch_narrow(const NarrowDesc& d0, hipStream_t st) {
+  NarrowDesc d = d0;
+  const int K = 1 << d.k, N = 1 << d.n;
+  int mx = d.k > d.n ? d.k : d.n;
+  d.q = d.m < 11 - mx ? d.m : 11 - mx;
+  // tile output bits: the q lowest m positions and all n positions of C
+  const uint64_t full = (d.m + d.n) >= 64 ? ~0ull : ((1ull << (d.m + d.n)) - 1);
+  const uint64_t npos = ~d.cmask & full;
+  uint64_t mlow = 0, mm = d.cmask;
+  for (int j = 0; j < d.q; ++j) {
+    uint64_t low = mm & (~mm + 1);
+    mlow |= low;
+    mm ^= low;
+  }
+  d.tmask = mlow | npos;
+  // positions, in tile order, of the row bits and of the n bits
+  uint64_t rt = 0, nt = 0;
+  int pos = 0;
+  for (int bit = 0; bit < 64; ++bit) {
+    const uint64_t v = 1ull << bit;
+    if (!(d.tmask & v)) continue;
+    if (mlow & v) rt |= 1ull << pos;
+    if (npos & v) nt |= 1ull << pos;
+    ++pos;
+  }
+  d.rt = rt;
+  d.nt = nt;
+  const int64_t tiles = (int64_t(1) << (d.m - d.q)) * d.nb;
+  const int blocks = (int)(tiles < 65536 ? tiles : 65536);
+  const int TM = 1 << d.q, KP = K == 1 ? 1 : K + 1;
+  d.a_elems = TM * KP > TM * N ? TM * KP : TM * N;
+  const size_t lds = (size_t)(d.a_elems + N * K) * sizeof(float2);
+  const int nch = N >= 8 ? 8 : N;
+  switch (nch) {
+    case 1:
+      hipLaunchKernelGGL(k_narrow<1>, dim3(blocks), dim3(256), lds, st, d);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_narrow<2>, dim3(blocks), dim3(256), lds, st, d);
+      break;
+    case 4:
+      hipLaunchKernelGGL(k_narrow<4>, dim3(blocks), dim3(256), lds, st, d);
+      break;
+    default:
+      hipLaunchKernelGGL(k_narrow<8>, dim3(blocks), dim3(256), lds, st, d);
+      break;
+  }
+}
+
+}  // namespace ltn

@@ -96,6 +96,23 @@ struct PermuteDesc {
 };
 void launch_permute(const float2* in, float2* out, const PermuteDesc& d, hipStream_t st);
 
+// Narrow step C[merge(m, n)] = sum_k A[m][k] B[n][k] (k + n <= 10, n <= 6), A and B
+// row-major per slice, complex64; cmask = C positions of the m bits.
+struct NarrowDesc {
+  const float2* A;
+  const float2* B;
+  float2* C;
+  int64_t sA, sB, sC;
+  int32_t m, k, n, nb;
+  uint64_t cmask;
+  uint32_t* scale_c;  // per-slice max slots of C, or null
+  // filled by launch_narrow
+  int32_t q, a_elems;
+  uint64_t tmask, rt, nt;
+};
+bool narrow_fits(int m, int k, int n);
+void launch_narrow(const NarrowDesc& d, hipStream_t st);
+
 int gemm_config_count(int mode);
 bool gemm_config_fits(int cfg, int m, int k, int n, int mode);
 const char* gemm_config_name(int cfg, int mode);

@@ -8,6 +8,7 @@
 // rule makes the same choices.
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <map>
 #include <unordered_map>
 
@@ -398,6 +399,180 @@ std::vector<int32_t> slice_refine(const Tree& tree, int t, const std::vector<int
   return best;
 }
 
+// Subtree reconfiguration. Node costs 2^|s_v - S| as 128-bit integers that
+// saturate at 2^120; a sweep visits every contraction node once (ids of the
+// tree at the start of the sweep), then the tree is written out again in
+// post order.
+namespace {
+using u128 = unsigned __int128;
+const u128 kSat = (u128)1 << 120;
+inline u128 sat(u128 x) { return x < kSat ? x : kSat; }
+inline u128 pow2_sat(int e) { return e < 120 ? ((u128)1 << e) : kSat; }
+}  // namespace
+
+std::vector<int32_t> reconfigure(const std::vector<IdSet>& leaves, const std::vector<int32_t>& path,
+                                 int k, int sweeps, const IdSet& S, int t) {
+  require(k >= 2 && k <= 16, "subtree size k must be in 2..16");
+  const int32_t L = (int32_t)leaves.size();
+  const int32_t n = L + (int32_t)path.size() / 2;
+  std::vector<IdSet> sets(leaves.begin(), leaves.end());
+  std::vector<std::pair<int32_t, int32_t>> kids(L, {-1, -1});
+  for (size_t s = 0; s + 1 < path.size(); s += 2) {
+    sets.push_back(set_xor(sets[path[s]], sets[path[s + 1]]));
+    kids.push_back({path[s], path[s + 1]});
+  }
+  auto unsliced = [&](const IdSet& x) { return (int)set_minus(x, S).size(); };
+  auto node_cost = [&](const IdSet& a, const IdSet& b) { return pow2_sat(unsliced(set_or(a, b))); };
+  std::vector<int32_t> out_path(path);
+  for (int sw = 0; sw < sweeps; ++sw) {
+    bool improved = false;
+    for (int32_t v = L; v < n; ++v) {
+      std::vector<int32_t> front{v};
+      while ((int)front.size() < k) {
+        int32_t pick = -1;
+        int psz = -1;
+        for (int32_t u : front) {
+          if (kids[u].first < 0) continue;
+          int sz = unsliced(set_or(sets[kids[u].first], sets[kids[u].second]));
+          if (sz > psz || (sz == psz && u < pick)) {
+            psz = sz;
+            pick = u;
+          }
+        }
+        if (pick < 0) break;
+        front.erase(std::find(front.begin(), front.end(), pick));
+        front.push_back(kids[pick].first);
+        front.push_back(kids[pick].second);
+      }
+      const int m = (int)front.size();
+      if (m < 3) continue;
+      // inner nodes in pre order (node, left subtree, right subtree)
+      std::vector<int32_t> inner;
+      std::vector<int32_t> stack{v};
+      while (!stack.empty()) {
+        int32_t u = stack.back();
+        stack.pop_back();
+        if (std::find(front.begin(), front.end(), u) != front.end()) continue;
+        inner.push_back(u);
+        stack.push_back(kids[u].second);
+        stack.push_back(kids[u].first);
+      }
+      u128 old = 0;
+      for (int32_t u : inner) old = sat(old + node_cost(sets[kids[u].first], sets[kids[u].second]));
+      if (old >= kSat) continue;
+      const uint32_t full = (1u << m) - 1;
+      // frontier tensors without S as bit sets over their local index universe
+      IdSet uni;
+      for (int32_t u : front) uni = set_or(uni, set_minus(sets[u], S));
+      const int W = std::max<int>(1, ((int)uni.size() + 63) / 64);
+      std::vector<uint64_t> tens((size_t)(full + 1) * W, 0);
+      for (int i = 0; i < m; ++i) {
+        uint64_t* dst = &tens[(size_t)(1u << i) * W];
+        for (int32_t x : set_minus(sets[front[i]], S)) {
+          int pos = (int)(std::lower_bound(uni.begin(), uni.end(), x) - uni.begin());
+          dst[pos / 64] |= 1ull << (pos % 64);
+        }
+      }
+      for (uint32_t M = 1; M <= full; ++M) {
+        uint32_t low = M & (~M + 1);
+        if (low == M) continue;
+        const uint64_t* a = &tens[(size_t)(M ^ low) * W];
+        const uint64_t* b = &tens[(size_t)low * W];
+        uint64_t* d = &tens[(size_t)M * W];
+        for (int j = 0; j < W; ++j) d[j] = a[j] ^ b[j];
+      }
+      auto rank_of = [&](uint32_t M) {
+        int r = 0;
+        const uint64_t* a = &tens[(size_t)M * W];
+        for (int j = 0; j < W; ++j) r += __builtin_popcountll(a[j]);
+        return r;
+      };
+      auto union_rank = [&](uint32_t A, uint32_t B) {
+        int r = 0;
+        const uint64_t* a = &tens[(size_t)A * W];
+        const uint64_t* b = &tens[(size_t)B * W];
+        for (int j = 0; j < W; ++j) r += __builtin_popcountll(a[j] | b[j]);
+        return r;
+      };
+      std::vector<u128> best(full + 1, 0);
+      std::vector<uint32_t> choice(full + 1, 0);
+      for (uint32_t M = 1; M <= full; ++M) {
+        if ((M & (M - 1)) == 0) continue;
+        if (t >= 0 && M != full && rank_of(M) > t) {
+          best[M] = kSat;
+          continue;
+        }
+        bool have = false;
+        u128 bc = 0;
+        uint32_t bsub = 0;
+        for (uint32_t sub = (M - 1) & M; sub; sub = (sub - 1) & M) {
+          uint32_t o = M ^ sub;
+          if (sub >= o) continue;
+          u128 c = sat(sat(best[sub] + best[o]) + pow2_sat(union_rank(sub, o)));
+          if (!have || c < bc) {
+            have = true;
+            bc = c;
+            bsub = sub;
+          }
+        }
+        best[M] = bc;
+        choice[M] = bsub;
+      }
+      if (best[full] >= old) continue;
+      improved = true;
+      std::vector<int32_t> pool;
+      for (int32_t u : inner)
+        if (u != v) pool.push_back(u);
+      // rebuild in post order: children first, new ids taken from the end of the pool
+      std::function<int32_t(uint32_t, bool)> assign = [&](uint32_t M, bool root) -> int32_t {
+        if ((M & (M - 1)) == 0) return front[__builtin_ctz(M)];
+        int32_t a = assign(choice[M], false);
+        int32_t b = assign(M ^ choice[M], false);
+        int32_t u = v;
+        if (!root) {
+          u = pool.back();
+          pool.pop_back();
+        }
+        kids[u] = {a, b};
+        sets[u] = set_xor(sets[a], sets[b]);
+        return u;
+      };
+      assign(full, true);
+    }
+    // post order from the root, left child first
+    std::vector<int32_t> order;
+    std::vector<std::pair<int32_t, bool>> st{{n - 1, false}};
+    while (!st.empty()) {
+      auto [u, done] = st.back();
+      st.pop_back();
+      if (kids[u].first < 0) continue;
+      if (done) {
+        order.push_back(u);
+      } else {
+        st.push_back({u, true});
+        st.push_back({kids[u].second, false});
+        st.push_back({kids[u].first, false});
+      }
+    }
+    std::vector<int32_t> newid(n, 0);
+    for (int32_t i = 0; i < L; ++i) newid[i] = i;
+    out_path.clear();
+    for (int32_t u : order) {
+      newid[u] = L + (int32_t)out_path.size() / 2;
+      out_path.push_back(newid[kids[u].first]);
+      out_path.push_back(newid[kids[u].second]);
+    }
+    sets.resize(L);
+    kids.resize(L);
+    for (size_t s = 0; s + 1 < out_path.size(); s += 2) {
+      sets.push_back(set_xor(sets[out_path[s]], sets[out_path[s + 1]]));
+      kids.push_back({out_path[s], out_path[s + 1]});
+    }
+    if (!improved) break;
+  }
+  return out_path;
+}
+
 std::vector<int32_t> slice_greedy_overhead(const Tree& tree, int t, const std::vector<int32_t>& pre) {
   std::vector<int32_t> S = pre;
   if (t < 0) return S;
@@ -509,6 +684,8 @@ extern "C" ltn_status ltn_path_search(const ltn_network* net, int32_t t, const i
     require(o->n_alpha >= 1 && o->alphas && o->n_tau >= 1 && o->taus && o->n_seeds >= 1,
             "empty search grid");
     require(n_pre >= 0 && (n_pre == 0 || pre), "bad pre list");
+    require(o->reconf_k == 0 || (o->reconf_k >= 3 && o->reconf_k <= 16 && o->reconf_sweeps >= 0),
+            "reconf_k must be 0 or in 3..16, reconf_sweeps >= 0");
     std::vector<int32_t> p(pre, pre + n_pre);
     IdSet ex(p.begin(), p.end());
     std::sort(ex.begin(), ex.end());
@@ -522,7 +699,13 @@ extern "C" ltn_status ltn_path_search(const ltn_network* net, int32_t t, const i
         int seeds = o->taus[it] > 0.0 ? o->n_seeds : 1;
         for (int sd = 0; sd < seeds; ++sd, ++trial) {
           auto path = greedy(n.sets, ex, o->alphas[ia], o->taus[it], o->seed_base + (uint64_t)sd);
+          if (o->reconf_k >= 3) path = reconfigure(n.sets, path, o->reconf_k, o->reconf_sweeps, ex, -1);
           auto S = slice_finder(n.sets, path.data(), t, p);
+          if (o->reconf_k >= 3 && t >= 0) {
+            IdSet ss(S.begin(), S.end());
+            std::sort(ss.begin(), ss.end());
+            path = reconfigure(n.sets, path, o->reconf_k, o->reconf_sweeps, ss, t);
+          }
           Tree tr = Tree::build(n.sets, path.data());
           IdSet ss(S.begin(), S.end());
           std::sort(ss.begin(), ss.end());
@@ -588,5 +771,23 @@ extern "C" ltn_status ltn_slice_greedy_overhead(const ltn_network* net, const in
     require((int32_t)S.size() <= cap, "S_out too small", LTN_E_NOMEM);
     std::copy(S.begin(), S.end(), S_out);
     *n_sliced = (int32_t)S.size();
+  });
+}
+
+extern "C" ltn_status ltn_tree_reconfigure(const ltn_network* net, const int32_t* path, int32_t k,
+                                           int32_t sweeps, const int32_t* S, int32_t n_sliced,
+                                           int32_t t, int32_t* path_out) {
+  return guarded([&] {
+    Net n = Net::from_abi(net, false);
+    require(path && path_out, "NULL argument");
+    require(sweeps >= 0, "sweeps must be >= 0");
+    require(n_sliced >= 0 && (n_sliced == 0 || S), "bad slicing set");
+    const int32_t L = (int32_t)n.sets.size();
+    Tree::build(n.sets, path);  // validates the SSA path
+    IdSet s(S, S + n_sliced);
+    std::sort(s.begin(), s.end());
+    std::vector<int32_t> p(path, path + 2 * std::max(0, L - 1));
+    auto r = reconfigure(n.sets, p, k, sweeps, s, t);
+    std::copy(r.begin(), r.end(), path_out);
   });
 }

@@ -43,7 +43,8 @@ struct ltn_plan_impl {
   std::vector<ParamLeaf> pl;
   std::vector<int32_t> sl_bits, out_bits;
   // kernel choice per mode and step: kind 0 = generic (tk threads per
-  // output), 1 = complex64 MFMA GEMM, 2 = split MFMA GEMM (cfg, swap)
+  // output), 1 = complex64 MFMA GEMM, 2 = split MFMA GEMM (cfg, swap),
+  // 3 = narrow-step kernel (swap: rows taken from the B operand)
   struct Choice {
     int kind = 0, cfg = -1, swap = 0, tk = 1;
   };
@@ -128,6 +129,24 @@ void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena, int mode) {
   const uint64_t cm = sp.c_mask_a, full = (sp.m + sp.n) >= 64 ? ~0ull : ((1ull << (sp.m + sp.n)) - 1);
   const auto& ch = r.choice[mode][s];
   const bool split = mode != LTN_C64;
+  if (ch.kind == 3) {
+    NarrowDesc d{};
+    const bool sw = ch.swap;
+    d.A = sw ? B : A;
+    d.B = sw ? A : B;
+    d.C = C;
+    d.sA = int64_t(1) << (sw ? tb.rank : ta.rank);
+    d.sB = int64_t(1) << (sw ? ta.rank : tb.rank);
+    d.sC = int64_t(1) << tc.rank;
+    d.m = sw ? sp.n : sp.m;
+    d.n = sw ? sp.m : sp.n;
+    d.k = sp.k;
+    d.cmask = sw ? (~cm & full) : cm;
+    d.nb = nb;
+    if (mode == LTN_SPLIT_F16) d.scale_c = slot(p, sp.out);
+    launch_narrow(d, r.st);
+    return;
+  }
   if (ch.kind > 0) {
     GemmDesc d{};
     bool sw = ch.swap;
@@ -357,6 +376,15 @@ extern "C" ltn_status ltn_bind(ltn_plan* p, void* d_ws, size_t bytes, int32_t gr
                 ch.swap = sw;
               }
             }
+          }
+        }
+        // steps with many output rows and no MFMA tile: the narrow kernel
+        if (ch.kind == 0 && sp.m + sp.n >= 12) {
+          bool sw = sp.n > sp.m;
+          if (sw ? narrow_fits(sp.n, sp.k, sp.m) : narrow_fits(sp.m, sp.k, sp.n)) {
+            ch.kind = 3;
+            ch.cfg = 0;
+            ch.swap = sw;
           }
         }
         r->choice[mode].push_back(ch);
@@ -594,7 +622,8 @@ void drop_graphs(ltn_plan* p) {
 
 // Candidates: every MFMA tile configuration that fits the step in either
 // operand role (split tiles first in the split modes, then complex64 tiles),
-// and the generic kernel with 1, 8 or 64 threads per output on small steps.
+// the narrow-step kernel in either role (k + n <= 10), and the generic
+// kernel with 1, 8 or 64 threads per output on small steps.
 // Cache entries: [kind * 1000 + cfg, swap] for MFMA kinds, [-tk, 0] for the
 // generic kernel.
 extern "C" ltn_status ltn_autotune(ltn_plan* p, int32_t mode, const char* cache_path) {
@@ -648,6 +677,14 @@ extern "C" ltn_status ltn_autotune(ltn_plan* p, int32_t mode, const char* cache_
                 cands.push_back(ch);
               }
         }
+        for (int sw = 0; sw < 2; ++sw)
+          if (sw ? narrow_fits(sp.n, sp.k, sp.m) : narrow_fits(sp.m, sp.k, sp.n)) {
+            Choice ch;
+            ch.kind = 3;
+            ch.cfg = 0;
+            ch.swap = sw;
+            cands.push_back(ch);
+          }
         // the generic kernel only competes on small steps (or when no tile fits)
         if (cands.empty() || sp.m + sp.k + sp.n <= 22)
           for (int tk : {1, 8, 64})
@@ -707,6 +744,39 @@ extern "C" ltn_status ltn_profile_steps(ltn_plan* p, uint64_t first, int32_t mod
     for (int s = 0; s < (int)p->steps.size(); ++s) HIPCHECK(hipEventElapsedTime(&ms_out[s], ev[s], ev[s + 1]));
     for (auto& e : ev) (void)hipEventDestroy(e);
     check_launch();
+  });
+}
+
+extern "C" ltn_status ltn_set_step_kernel(ltn_plan* p, int32_t step, int32_t mode, int32_t kind,
+                                          int32_t cfg, int32_t swap, int32_t tk) {
+  return guarded([&] {
+    require(p && p->rt, "plan is not bound");
+    require(step >= 0 && step < (int32_t)p->steps.size(), "step out of range");
+    check_mode(mode);
+    const StepPlan& sp = p->steps[step];
+    const int m = swap ? sp.n : sp.m, n = swap ? sp.m : sp.n;
+    ltn_plan_impl::Choice c;
+    if (kind == 0) {
+      require(tk == 1 || tk == 8 || tk == 64, "tk must be 1, 8 or 64");
+      c.tk = tk;
+    } else if (kind == 1 || kind == 2) {
+      require(kind == 1 || mode != LTN_C64, "split GEMM kernels need a split mode");
+      const int km = kind == 2 ? mode : LTN_C64;
+      require(cfg >= 0 && cfg < gemm_config_count(km) && gemm_config_fits(cfg, m, sp.k, n, km),
+              "tile configuration does not fit the step");
+      c.kind = kind;
+      c.cfg = cfg;
+      c.swap = swap ? 1 : 0;
+    } else if (kind == 3) {
+      require(narrow_fits(m, sp.k, n), "the narrow kernel does not fit the step");
+      c.kind = 3;
+      c.cfg = 0;
+      c.swap = swap ? 1 : 0;
+    } else {
+      require(false, "unknown kernel kind");
+    }
+    drop_graphs(p);
+    p->rt->choice[mode][step] = c;
   });
 }
 

@@ -196,6 +196,15 @@ def slice_refine(net: Network, path, t: int, S: Sequence[int], n_fixed: int = 0,
                                   "accepted": st.accepted, "dropped": st.dropped}
 
 
+def tree_reconfigure(net: Network, path, k: int = 8, sweeps: int = 1, S: Sequence[int] = (),
+                     t: int = -1):
+    """Subtree reconfiguration; returns the new SSA path."""
+    out = (C.c_int32 * max(1, 2 * (net.n_leaves - 1)))()
+    L.check(L.lib().ltn_tree_reconfigure(C.byref(net.view), _path_array(path), k, sweeps,
+                                         L.i32_array(list(S)), len(S), t, out))
+    return [(out[2 * j], out[2 * j + 1]) for j in range(net.n_leaves - 1)]
+
+
 def slice_greedy_overhead(net: Network, path, t: int, pre: Sequence[int] = ()) -> List[int]:
     """Greedy least-overhead slicer (comparison baseline for Algorithm 1)."""
     cap = net.n_indices + 1
@@ -208,11 +217,12 @@ def slice_greedy_overhead(net: Network, path, t: int, pre: Sequence[int] = ()) -
 
 
 def path_search(net: Network, t: int, pre: Sequence[int] = (), alphas=(1.0,), taus=(0.0,),
-                n_seeds: int = 1, seed_base: int = 0):
-    """Randomised greedy trials + slice finder; returns (path, S, best trial)."""
+                n_seeds: int = 1, seed_base: int = 0, reconf_k: int = 0, reconf_sweeps: int = 4):
+    """Randomised greedy trials (optionally improved by subtree
+    reconfiguration) + slice finder; returns (path, S, best trial)."""
     a = (C.c_double * len(alphas))(*alphas)
     tt = (C.c_double * len(taus))(*taus)
-    o = L.SearchOpts(len(alphas), a, len(taus), tt, n_seeds, seed_base)
+    o = L.SearchOpts(len(alphas), a, len(taus), tt, n_seeds, seed_base, reconf_k, reconf_sweeps)
     path = (C.c_int32 * max(1, 2 * (net.n_leaves - 1)))()
     cap = net.n_indices + 1
     S = (C.c_int32 * cap)()

@@ -12,7 +12,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 from . import _lib as L
-from .network import Network, path_search, SEARCH_ALPHAS, SEARCH_TAUS, SEARCH_SEEDS
+from .network import (Network, path_search, slice_refine, tree_costs, SEARCH_ALPHAS, SEARCH_TAUS,
+                      SEARCH_SEEDS)
 
 
 def _torch():
@@ -149,6 +150,12 @@ class Plan:
         L.check(L.lib().ltn_profile_steps(self._h, first, L.MODES[mode], out))
         return np.asarray(out[:n], dtype=np.float64)
 
+    def set_step_kernel(self, k: int, mode: str, kind: int, cfg: int = 0, swap: int = 0,
+                        tk: int = 1) -> None:
+        """Force the kernel of step k in a mode (kind 0 generic with tk, 1
+        complex64 MFMA, 2 split MFMA, 3 narrow)."""
+        L.check(L.lib().ltn_set_step_kernel(self._h, k, L.MODES[mode], kind, cfg, swap, tk))
+
     def step_kernel(self, k: int, mode: str = "c64"):
         """(kind, cfg, swap, tk): kind 0 generic, 1 complex64 MFMA, 2 split MFMA."""
         kind, cfg, sw, tk = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
@@ -182,9 +189,13 @@ class Prepared:
 
 
 def prepare(workload, alphas=SEARCH_ALPHAS, taus=SEARCH_TAUS, n_seeds=SEARCH_SEEDS,
-            seed_base: int = 0) -> Prepared:
+            seed_base: int = 0, reconf_k: int = 0, reconf_sweeps: int = 4,
+            refine_seeds: int = 0) -> Prepared:
     """Host planner for a workload: network (with absorption), randomised
-    greedy path search and lifetime-based slicing under its max rank."""
+    greedy path search (optionally with subtree reconfiguration) and
+    lifetime-based slicing under its max rank; with refine_seeds > 0 the
+    slicing set is then refined (Algorithms 2-4) with seeds 0..refine_seeds-1
+    and the best result (C(B,S), |S|, seed) is kept."""
     w = workload
     net = Network.from_circuit(w.circuit, w.open_qubits, w.closed_bits)
     pre = []
@@ -193,7 +204,16 @@ def prepare(workload, alphas=SEARCH_ALPHAS, taus=SEARCH_TAUS, n_seeds=SEARCH_SEE
         # last open qubit first so that slice id == bitstring
         pre = list(reversed(net.open_ids))
     t = w.max_rank if w.max_rank is not None else -1
-    path, S, trial = path_search(net, t, pre, alphas, taus, n_seeds, seed_base)
+    path, S, trial = path_search(net, t, pre, alphas, taus, n_seeds, seed_base, reconf_k,
+                                 reconf_sweeps)
+    if refine_seeds > 0 and t >= 0:
+        best = None
+        for sd in range(refine_seeds):
+            R, _ = slice_refine(net, path, t, S, n_fixed=len(pre), seed=sd)
+            key = (tree_costs(net, path, R).sliced, len(R), sd)
+            if best is None or key < best[0]:
+                best = (key, R)
+        S = best[1]
     return Prepared(w, net, path, S, trial, pre)
 
 

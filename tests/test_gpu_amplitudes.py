@@ -183,6 +183,30 @@ def test_rqc30_full_size(torch):
 TOL_SPLIT = 5e-4
 
 
+@pytest.mark.parametrize("mode", ["c64", "split_f16", "split_bf16"])
+def test_rqc30_reconfigured_path(torch, mode):
+    """The 30-qubit workload on the path improved by subtree reconfiguration
+    (different tree, same amplitudes): all slices, autotuned, against the
+    stored oracle amplitudes."""
+    import paper_2205_00393_amd as P
+    path = os.path.join(GOLDEN, "rqc30_amplitudes.npy")
+    if not os.path.exists(path):
+        pytest.skip("golden rqc30 amplitudes not generated")
+    ref = np.load(path)
+    w = make_workload("rqc30")
+    pr = P.prepare(w, reconf_k=8)
+    plan = pr.plan()
+    n = 1 << len(pr.sliced)
+    banner(f"rqc30 reconfigured path |S|={len(pr.sliced)} {mode}")
+    plan.bind(batch=n)
+    plan.autotune(mode)
+    out = plan.execute_range(0, n, mode=mode)
+    torch.cuda.synchronize()
+    err = rel_l2(out.cpu().numpy(), ref)
+    banner(f"rqc30 reconfigured {mode} rel err {err:.3e}")
+    assert err < (TOL_C64 if mode == "c64" else TOL_SPLIT)
+
+
 @pytest.mark.parametrize("mode", ["split_f16", "split_bf16"])
 @pytest.mark.parametrize("fat", [1, 0])
 def test_reduced_split_precision(torch, mode, fat):

@@ -1,0 +1,92 @@
+"""Every kernel a step can run, forced step by step through
+ltn_set_step_kernel: narrow-step kernel in both operand roles, generic
+kernel with 1, 8 and 64 threads per output, complex64 MFMA tiles, and the
+split tiles in the split modes. Each forced plan must reproduce the
+brute-force state-vector amplitudes (complex64 <= 1e-4, split <= 5e-4)."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import banner, rel_l2
+from tests.test_gpu_amplitudes import _reduced, _sv
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = {
+    "narrow_rows_a": [(3, 0, 0, 1)],
+    "narrow_rows_b": [(3, 0, 1, 1)],
+    "generic_tk1": [(0, -1, 0, 1)],
+    "generic_tk8": [(0, -1, 0, 8)],
+    "generic_tk64": [(0, -1, 0, 64)],
+    "mfma_c64": [(1, c, s, 1) for s in (0, 1) for c in range(10)],
+    "mfma_split": [(2, c, s, 1) for s in (0, 1) for c in range(10)],
+}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def prepared():
+    """Narrow steps of every shape: a reconfigured path at t = 14."""
+    import paper_2205_00393_amd as P
+    w = _reduced(rows=4, cols=5, cycles=10, n_open=6, t=14)
+    pr = P.prepare(w, alphas=(0.5, 1.0), taus=(0.0, 0.3), n_seeds=3, reconf_k=6)
+    return w, pr, _sv(w)
+
+
+@pytest.fixture(scope="module")
+def prepared_fat():
+    """Steps large enough for the MFMA tiles: a greedy path at t = 16."""
+    import paper_2205_00393_amd as P
+    w = _reduced(rows=4, cols=5, cycles=12, n_open=6, t=16)
+    pr = P.prepare(w, alphas=(0.5, 1.0), taus=(0.0, 0.3), n_seeds=3)
+    return w, pr, _sv(w)
+
+
+@pytest.mark.parametrize("mode", ["c64", "split_f16", "split_bf16"])
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_forced_kernel_variant(torch, prepared, prepared_fat, mode, variant):
+    import paper_2205_00393_amd as P
+    if variant == "mfma_split" and mode == "c64":
+        pytest.skip("split tiles need a split mode")
+    w, pr, ref = prepared_fat if variant.startswith("mfma") else prepared
+    plan = pr.plan()
+    n = 1 << len(pr.sliced)
+    plan.bind(batch=min(n, 4), budget_bytes=1 << 30)
+    forced = []
+    for k, st in enumerate(plan.steps()):
+        for kind, cfg, swap, tk in VARIANTS[variant]:
+            try:
+                plan.set_step_kernel(k, mode, kind, cfg, swap, tk)
+            except P.LtnError:
+                continue
+            forced.append((k, st["m"], st["k"], st["n"]))
+            break
+    banner(f"forced {variant} in {mode} on {len(forced)} of {len(plan.steps())} steps")
+    assert forced, "no step accepts this kernel"
+    out = plan.execute_range(0, n, mode=mode)
+    torch.cuda.synchronize()
+    err = rel_l2(out.cpu().numpy(), ref)
+    banner(f"forced {variant} {mode}: rel err {err:.3e}")
+    assert err < (1e-4 if mode == "c64" else 5e-4)
+
+
+def test_set_step_kernel_rejects_misfits(torch, prepared):
+    import paper_2205_00393_amd as P
+    w, pr, ref = prepared
+    plan = pr.plan()
+    plan.bind(batch=1, budget_bytes=1 << 30)
+    with pytest.raises(P.LtnError, match="split"):
+        plan.set_step_kernel(0, "c64", 2, 0, 0, 1)
+    with pytest.raises(P.LtnError, match="tk"):
+        plan.set_step_kernel(0, "c64", 0, -1, 0, 3)
+    with pytest.raises(P.LtnError, match="kind"):
+        plan.set_step_kernel(0, "c64", 7, 0, 0, 1)
+    big = [k for k, st in enumerate(plan.steps()) if st["k"] + st["n"] > 10 and st["k"] + st["m"] > 10]
+    for k in big[:1]:
+        with pytest.raises(P.LtnError, match="narrow"):
+            plan.set_step_kernel(k, "c64", 3, 0, 0, 1)

@@ -135,3 +135,77 @@ def test_refiner_reaches_brute_force_optimum_mostly():
             tot += 1
             hits += tr.sliced_cost(R) == _brute_min(tr, t, len(S))
     assert hits >= 0.6 * tot, (hits, tot)
+
+
+# ---------------------------------------------------------------------------
+# Subtree reconfiguration
+
+
+def _all_tree_costs(sets, Sset):
+    """Brute force: the cheapest total node cost 2^|s_v - S| over every way
+    of contracting the given tensors pairwise (no subset table)."""
+    best = None
+    items = [frozenset(s) for s in sets]
+
+    def rec(items, acc):
+        nonlocal best
+        if best is not None and acc >= best:
+            return
+        if len(items) == 1:
+            best = acc
+            return
+        for i in range(len(items)):
+            for j in range(i + 1, len(items)):
+                a, b = items[i], items[j]
+                c = 1 << len((a | b) - Sset)
+                rest = [items[x] for x in range(len(items)) if x not in (i, j)] + [a ^ b]
+                rec(rest, acc + c)
+
+    rec(items, 0)
+    return best
+
+
+def _is_ssa_cover(L, path):
+    seen = set()
+    for k, (a, b) in enumerate(path):
+        v = L + k
+        if not (0 <= a < v and 0 <= b < v and a != b) or a in seen or b in seen:
+            return False
+        seen.update((a, b))
+    return len(path) == L - 1
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_reconfigure_whole_tree_is_optimal_on_tiny_networks(seed):
+    """With k >= number of leaves the root's frontier is every leaf, so one
+    sweep must reach the cheapest contraction order (brute force over all
+    pairwise orders)."""
+    idx, n, opens = random_network(seed, 6, 8, 2)
+    p = opl.greedy_path(idx, 1.0, 0.0, seed)
+    p2 = opl.reconfigure(idx, p, k=6, sweeps=1)
+    assert _is_ssa_cover(len(idx), p2)
+    assert opl.Tree(idx, p2).cost() == _all_tree_costs(idx, frozenset())
+    # with a slicing set the sliced node costs are minimised instead
+    S = [0, 3]
+    p3 = opl.reconfigure(idx, p, k=6, sweeps=1, S=S)
+    assert opl.Tree(idx, p3).sliced_cost(S) == _all_tree_costs(idx, frozenset(S)) * 4
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_reconfigure_invariants(seed):
+    idx, n, opens = random_network(seed, 14, 24, 3)
+    p = opl.greedy_path(idx, 0.5, 1.0, seed)
+    tr = opl.Tree(idx, p)
+    for k in (3, 5, 7):
+        p2 = opl.reconfigure(idx, p, k, sweeps=3)
+        tr2 = opl.Tree(idx, p2)
+        assert _is_ssa_cover(len(idx), p2)
+        assert tr2.sets[tr2.root] == tr.sets[tr.root]  # same output indices
+        assert tr2.cost() <= tr.cost()
+        mx = max(len(s) for s in tr2.sets)
+        t = max(1, mx - 2)
+        S = opl.slice_finder(tr2, t)
+        p3 = opl.reconfigure(idx, p2, k, sweeps=3, S=S, t=t)
+        tr3 = opl.Tree(idx, p3)
+        assert opl.fits(tr3, S, t)
+        assert tr3.sliced_cost(S) <= tr2.sliced_cost(S)

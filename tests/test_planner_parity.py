@@ -224,3 +224,29 @@ def test_slice_refiner_errors():
         P.slice_refine(cnet, p, 99, [], alpha=1.5)
     with pytest.raises(P.LtnError, match="repeated"):
         P.slice_refine(cnet, p, 99, [0, 0])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_reconfigure_bit_exact_random(seed):
+    idx, n, opens = random_network(seed, 16, 28, 3)
+    data = [np.ones([2] * len(ix), dtype=np.complex64) for ix in idx]
+    cnet = P.Network.from_arrays(idx, data, opens, n)
+    p = opl.greedy_path(idx, 0.5, 1.0, seed)
+    for k in (3, 6, 9):
+        want = opl.reconfigure(idx, p, k, sweeps=3)
+        assert P.tree_reconfigure(cnet, p, k, 3) == want
+        tr = opl.Tree(idx, want)
+        t = max(1, max(len(s) for s in tr.sets) - 2)
+        S = opl.slice_finder(tr, t)
+        assert P.tree_reconfigure(cnet, want, k, 2, S, t) == opl.reconfigure(idx, want, k, 2, S, t)
+
+
+@pytest.mark.parametrize("name", ["rqc12", "rqc30", "rqc20_grad"])
+def test_path_search_with_reconfiguration_bit_exact(name):
+    w, onet, cnet = _both(name)
+    pre = list(reversed(onet.open_ids)) if w.slice_open else []
+    t = w.max_rank if w.max_rank is not None else -1
+    kw = dict(alphas=(1.0, 0.5), taus=(0.0, 0.3), n_seeds=2, reconf_k=6, reconf_sweeps=2)
+    want = opl.path_search(onet.indices, t, pre, **kw)
+    got = P.path_search(cnet, t, pre, **kw)
+    assert got == (want[0], want[1], want[2])
