@@ -275,7 +275,10 @@ typedef struct ltn_options {
   int32_t batch;         /* slices per batch; 0 = as many as fit          */
   int32_t fat_threshold; /* steps with min(k, n, m) bits >= this go to the
                             MFMA GEMM (0 = library default)                */
-  int32_t reserved;
+  int32_t fuse_rank;     /* > 0: fuse runs of stem steps that absorb small
+                            tensors (secondary slicing, Sec. 5.2) when every
+                            working tensor has rank <= fuse_rank (<= 11);
+                            0 = no fusion                                   */
 } ltn_options;
 
 /* Compile a plan (host only, no device call): validate the network, the
@@ -302,6 +305,21 @@ typedef struct ltn_plan_info {
   const int32_t* sliced_ids;    /* [n_sliced], bit order of slice ids     */
 } ltn_plan_info;
 ltn_status ltn_plan_describe(const ltn_plan* plan, ltn_plan_info* out);
+
+/* Fused sub-paths of a plan (secondary slicing, Sec. 5.2): group g covers
+ * the chain steps first_step[g] .. (in chain order, n_steps[g] of them; the
+ * last one is where it runs), fixes the |Sigma| = n_sigma[g] indices of its
+ * input that survive to its output, and works on tensors of at most
+ * 2^work_rank[g] elements per piece. Arrays of capacity cap; *n = number
+ * of groups. Host only. */
+ltn_status ltn_plan_groups(const ltn_plan* plan, int32_t* first_step, int32_t* n_steps,
+                           int32_t* n_sigma, int32_t* work_rank, int32_t cap, int32_t* n);
+
+/* Run fused sub-paths (enable != 0, the default after ltn_bind) or step
+ * by step in the forward pass of ltn_execute / ltn_execute_range. Gradient
+ * passes always run step by step (the adjoint reads every intermediate).
+ * Drops captured graphs. Errors: LTN_E_STATE if unbound. */
+ltn_status ltn_set_fusion(ltn_plan* plan, int32_t enable);
 
 /* Kernel classes a step can use. */
 enum { LTN_K_SMALL = 0, LTN_K_MFMA = 1 };

@@ -56,7 +56,7 @@ class RefineStats(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("max_rank", C.c_int32), ("batch", C.c_int32), ("fat_threshold", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("fuse_rank", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -107,6 +107,8 @@ SIGNATURES = {
     "ltn_execute_grad": [P, U64P, U64, I32, P, P, P],
     "ltn_autotune": [P, I32, C.c_char_p],
     "ltn_profile_steps": [P, U64, I32, C.POINTER(C.c_float)],
+    "ltn_plan_groups": [P, I32P, I32P, I32P, I32P, I32, I32P],
+    "ltn_set_fusion": [P, I32],
     "ltn_set_step_kernel": [P, I32, I32, I32, I32, I32, I32],
     "ltn_step_kernel": [P, I32, I32, I32P, I32P, I32P, I32P],
     "ltn_permute": [P, P, I32, I32P, C.c_int64, P],

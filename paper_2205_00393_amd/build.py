@@ -36,6 +36,7 @@ SOURCES = [
     ("k_mfma.hip", "hip"),
     ("k_permute.hip", "hip"),
     ("k_narrow.hip", "hip"),
+    ("k_fused.hip", "hip"),
 ]
 
 

@@ -53,7 +53,7 @@ __device__ __forceinline__ uint64_t pdep64(uint64_t x, uint64_t mask) {
 __device__ __forceinline__ void record_max(uint32_t* slot, float v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-  if ((threadIdx.x & 63) == 0 && v > 0.f) atomicMax(slot, __float_as_uint(v));
+  if ((threadIdx.x & 63) == 0) raise_max(slot, v);
 }
 
 // sigma = 2^(-floor(log2 max)), so that max * sigma lies in [1, 2)

@@ -27,7 +27,7 @@ __global__ void k_set_range(uint64_t* d, uint64_t base, int n) {
 __device__ __forceinline__ void record_max(uint32_t* slot, float v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-  if ((threadIdx.x & 63) == 0 && v > 0.f) atomicMax(slot, __float_as_uint(v));
+  if ((threadIdx.x & 63) == 0) raise_max(slot, v);
 }
 
 // one block per (leaf, slice); threads run over the leaf's elements
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256) void k_generic(GenericDesc d) {
     }
     if (d.scale_out && lane == 0) {
       if (b != bcur) {
-        if (bcur != ~0ull && vcur > 0.f) atomicMax(d.scale_out + bcur, __float_as_uint(vcur));
+        if (bcur != ~0ull) raise_max(d.scale_out + bcur, vcur);
         bcur = b;
         vcur = 0.f;
       }
@@ -295,9 +295,9 @@ __global__ __launch_bounds__(256) void k_generic(GenericDesc d) {
     if (same && b0 != ~0ull) {
       float v = vcur;
       for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-      if ((threadIdx.x & 63) == 0 && v > 0.f) atomicMax(d.scale_out + b0, __float_as_uint(v));
+      if ((threadIdx.x & 63) == 0) raise_max(d.scale_out + b0, v);
     } else if (!same && bcur != ~0ull && vcur > 0.f) {
-      atomicMax(d.scale_out + bcur, __float_as_uint(vcur));
+      raise_max(d.scale_out + bcur, vcur);
     }
   }
 }

@@ -58,6 +58,7 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowDesc d) {
   __syncthreads();
   const int64_t tiles = int64_t(1) << (d.m - q);
   const int64_t work = tiles * d.nb;
+  float vmax = 0.f;  // running maximum of |re|, |im| for the current slice
   for (int64_t it = blockIdx.x; it < work; it += gridDim.x) {
     const int64_t b = it / tiles, tile = it % tiles;
     const uint64_t m0 = (uint64_t)tile << q;
@@ -100,7 +101,6 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowDesc d) {
       }
     }
     __syncthreads();  // A tile no longer read: stage the outputs over it
-    float vmax = 0.f;
 #pragma unroll
     for (int i = 0; i < 8 / NCH; ++i) {
       const int w = tid + 256 * i;
@@ -127,9 +127,16 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowDesc d) {
       for (int t = tid; t < outs; t += 256) Cb[tT_lo[t & 63] | tT_hi[t >> 6]] = As[t];
     }
     if (d.scale_c) {
+      // flush the running maximum when the next tile of this block belongs
+      // to another slice (or there is none)
+      const int64_t nx = it + gridDim.x;
+      if (nx >= work || nx / tiles != b) {
+        float v = vmax;
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off, 64));
-      if ((tid & 63) == 0 && vmax > 0.f) atomicMax(d.scale_c + b, __float_as_uint(vmax));
+        for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+        if ((tid & 63) == 0) raise_max(d.scale_c + b, v);
+        vmax = 0.f;
+      }
     }
     __syncthreads();  // the next tile overwrites As and Bs
   }

@@ -10,6 +10,15 @@
 
 namespace ltn {
 
+// Raise a per-slice maximum slot (bits of a non-negative float) to v. The
+// slot only grows, so when a plain read already shows at least v the
+// atomic is skipped (a stale read can only cost an extra atomic); this
+// keeps thousands of tiles from serialising on one address.
+__device__ __forceinline__ void raise_max(uint32_t* slot, float v) {
+  const uint32_t bits = __float_as_uint(v);
+  if (v > 0.f && *reinterpret_cast<volatile uint32_t*>(slot) < bits) atomicMax(slot, bits);
+}
+
 constexpr int kMaxLeafRank = 32;
 
 // Gather of one leaf into its per-slice layout (Sec. 2.1.1: a sliced index
@@ -112,6 +121,27 @@ struct NarrowDesc {
 };
 bool narrow_fits(int m, int k, int n);
 void launch_narrow(const NarrowDesc& d, hipStream_t st);
+
+// Fused sub-path (secondary slicing): piece (b, sigma) reads the contiguous
+// 2^a elements of T_0 at sigma << a, runs the stages in LDS and writes W_L
+// to T_L at pdep(sigma, sig_out) | pdep(w, w_out).
+constexpr int kFusedMaxStages = 16;
+struct FusedStage {
+  const float2* Y;  // small operand, slice 0
+  int64_t sY;       // slice stride (elements)
+  int32_t m, k, n, yoff;  // yoff: element offset of Y in the LDS copy
+  uint64_t cmask;   // positions in W_j of the bits from W_{j-1}
+};
+struct FusedDesc {
+  const float2* X0;
+  float2* XL;
+  int64_t sX0, sXL;
+  int32_t a, nsig, c, rmax, y_elems, nstages, nb, pad;
+  uint64_t sig_out, w_out;
+  uint32_t* scale_c;  // per-slice max slots of T_L, or null
+  FusedStage st[kFusedMaxStages];
+};
+void launch_fused(const FusedDesc& d, hipStream_t st);
 
 int gemm_config_count(int mode);
 bool gemm_config_fits(int cfg, int m, int k, int n, int mode);

@@ -38,6 +38,163 @@ uint64_t place_block(std::vector<Block>& live, uint64_t size, int32_t begin, int
 
 }  // namespace
 
+namespace {
+
+bool has(const IdSet& sorted, int32_t x) { return std::binary_search(sorted.begin(), sorted.end(), x); }
+
+// The small operand Y of a step whose other operand is the chain tensor.
+// Only steps of low arithmetic intensity are fused (rank(Y) = k + n <= 6):
+// their cost is the HBM round trip that fusion removes; wider steps are
+// better served by the matrix cores one step at a time.
+bool small_other(const ltn_plan* p, const StepPlan& s, int32_t chain, int32_t* other) {
+  int32_t y = s.a == chain ? s.b : (s.b == chain ? s.a : -1);
+  if (y < 0) return false;
+  const int32_t ry = p->tensors[y].rank, n = ry - s.k;
+  if (ry > 6 || n > 6) return false;
+  *other = y;
+  return true;
+}
+
+// Build the group of the chain steps `steps` starting from tensor t0; false
+// if a working tensor exceeds 2^R elements or the sub-path is unsuitable.
+// Group of the chain steps `steps` from tensor t0 with the surviving
+// indices `sig` (sorted) fixed per piece; false if unsuitable.
+bool build_group(const ltn_plan* p, int32_t t0, const std::vector<int32_t>& steps, const IdSet& sig,
+                 FuseGroup* g) {
+  const int32_t tl = p->steps[steps.back()].out;
+  const IdSet& I0 = p->tensors[t0].idx;
+  const IdSet& IL = p->tensors[tl].idx;
+  auto without = [&](const IdSet& v) {
+    IdSet w;
+    for (int32_t x : v)
+      if (!has(sig, x)) w.push_back(x);
+    return w;
+  };
+  FuseGroup G;
+  G.t0 = t0;
+  G.tl = tl;
+  G.nsig = (int32_t)sig.size();
+  G.a = (int32_t)I0.size() - G.nsig;
+  // T_0's bits outside Sigma must be its lowest ones
+  for (int32_t j = 0; j < G.a; ++j)
+    if (has(sig, I0[j])) return false;
+  IdSet w_prev = without(I0);
+  G.rmax = (int32_t)w_prev.size();
+  int32_t chain = t0;
+  for (int32_t s : steps) {
+    const StepPlan& sp = p->steps[s];
+    int32_t y;
+    if (!small_other(p, sp, chain, &y)) return false;
+    const IdSet& Y = p->tensors[y].idx;
+    FuseStage st;
+    st.step = s;
+    st.other = y;
+    st.k = sp.k;
+    st.n = (int32_t)Y.size() - sp.k;
+    st.m = (int32_t)w_prev.size() - sp.k;
+    if (st.m < 0) return false;
+    for (int32_t j = 0; j < sp.k; ++j)
+      if (w_prev[j] != Y[j]) return false;  // contracted bits lowest on both sides
+    IdSet w_out = without(p->tensors[sp.out].idx);
+    if ((int32_t)w_out.size() != st.m + st.n) return false;
+    int32_t ia = sp.k;
+    for (int32_t q = 0; q < (int32_t)w_out.size(); ++q)
+      if (ia < (int32_t)w_prev.size() && w_prev[ia] == w_out[q]) {
+        st.cmask |= 1ull << q;
+        ++ia;
+      }
+    if (ia != (int32_t)w_prev.size()) return false;
+    G.rmax = std::max<int32_t>(G.rmax, (int32_t)w_out.size());
+    G.b_elems += 1 << p->tensors[y].rank;
+    G.st.push_back(st);
+    w_prev = w_out;
+    chain = sp.out;
+  }
+  G.c = (int32_t)w_prev.size();
+  for (int32_t q = 0; q < (int32_t)IL.size(); ++q) (has(sig, IL[q]) ? G.sig_out : G.w_out) |= 1ull << q;
+  // Sigma keeps its relative order from T_0 to T_L
+  {
+    IdSet a0, aL;
+    for (int32_t x : I0)
+      if (has(sig, x)) a0.push_back(x);
+    for (int32_t x : IL)
+      if (has(sig, x)) aL.push_back(x);
+    if (a0 != aL) return false;
+  }
+  if (G.b_elems > 2048 || (int)G.st.size() > kMaxFuseStages) return false;
+  *g = G;
+  return true;
+}
+
+// The indices of T_0 that survive to T_L, in T_0's bit order, are split:
+// the first ones (those among T_L's lowest 4 bits, then more up to working
+// rank R) are carried through every piece, the rest are fixed per piece.
+// Carrying the earliest-contracted survivors keeps a piece's input one
+// contiguous block of T_0 and makes its writes to T_L contiguous runs.
+bool make_group(const ltn_plan* p, int32_t t0, const std::vector<int32_t>& steps, int R, FuseGroup* g) {
+  const int32_t tl = p->steps[steps.back()].out;
+  const IdSet& I0 = p->tensors[t0].idx;
+  const IdSet& IL = p->tensors[tl].idx;
+  IdSet sl(IL.begin(), IL.end());
+  std::sort(sl.begin(), sl.end());
+  std::vector<int32_t> surv;  // in T_0 order
+  for (int32_t x : I0)
+    if (has(sl, x)) surv.push_back(x);
+  auto sig_after = [&](int q) {
+    IdSet s(surv.begin() + q, surv.end());
+    std::sort(s.begin(), s.end());
+    return s;
+  };
+  int q0 = 0;
+  for (int32_t q = 0; q < 4 && q < (int32_t)IL.size(); ++q)
+    if (std::find(surv.begin(), surv.end(), IL[q]) != surv.end()) ++q0;
+  FuseGroup G0;
+  if (q0 > (int)surv.size() || !build_group(p, t0, steps, sig_after(q0), &G0) || G0.rmax > R) return false;
+  const int extra = std::max(0, std::min(R - G0.rmax, (int)surv.size() - q0 - 3));
+  if (extra == 0) {
+    *g = G0;
+    return true;
+  }
+  FuseGroup G1;
+  if (!build_group(p, t0, steps, sig_after(q0 + extra), &G1) || G1.rmax > R) return false;
+  *g = G1;
+  return true;
+}
+
+// Greedy along the steps: start at a step whose larger operand has rank
+// >= R + 3 and whose other operand is small, extend along the chain while
+// the working tensors fit; keep sub-paths of at least two steps with
+// |Sigma| >= 3 (at least 8 pieces per slice).
+void find_groups(ltn_plan* p, int R) {
+  const int32_t ns = (int32_t)p->steps.size();
+  for (int32_t s = 0; s < ns; ++s) {
+    if (p->step_group[s] >= 0) continue;
+    const StepPlan& sp = p->steps[s];
+    const int32_t t0 = sp.a;
+    int32_t y;
+    if (p->tensors[t0].rank < R + 3 || !small_other(p, sp, t0, &y)) continue;
+    std::vector<int32_t> steps{s};
+    FuseGroup best;
+    bool have = false;
+    for (;;) {
+      FuseGroup g;
+      if (!make_group(p, t0, steps, R, &g)) break;
+      if (steps.size() >= 2 && g.nsig >= 3) {
+        best = g;
+        have = true;
+      }
+      const int32_t nxt = p->tensors[p->steps[steps.back()].out].consumer;
+      if (nxt < 0 || p->step_group[nxt] >= 0) break;
+      steps.push_back(nxt);
+    }
+    if (!have) continue;
+    for (auto& st : best.st) p->step_group[st.step] = (int32_t)p->groups.size();
+    p->groups.push_back(best);
+  }
+}
+
+}  // namespace
+
 extern "C" ltn_status ltn_plan_load(const ltn_network* net, const int32_t* path_ssa,
                                     int32_t n_sliced, const int32_t* sliced_ids,
                                     const ltn_options* opt, ltn_plan** out) {
@@ -199,12 +356,28 @@ extern "C" ltn_status ltn_plan_load(const ltn_network* net, const int32_t* path_
         if (open_pos[x] >= 0) p->out_sliced.push_back({j, p->n_open - 1 - open_pos[x]});
       }
     }
+    // fused sub-paths (secondary slicing, Sec. 5.2)
+    p->step_group.assign(p->steps.size(), -1);
+    std::vector<int32_t> keep_until(NT, -1);  // extended lifetimes (step index)
+    if (p->opt.fuse_rank > 0) {
+      require(p->opt.fuse_rank <= 11, "fuse_rank must be at most 11");
+      find_groups(p, p->opt.fuse_rank);
+      for (auto& g : p->groups) {
+        const int32_t last = g.st.back().step;
+        keep_until[g.t0] = last;
+        for (auto& s : g.st) keep_until[s.other] = last;
+      }
+    }
     // forward arena: leaves live from time 0, step k runs at time k+1, the
-    // reduction at time L
+    // reduction at time L; a fused sub-path runs at its last step, so T_0
+    // and the small tensors stay live until then
     {
       std::vector<Block> live;
       uint64_t high = 0;
-      auto t_end = [&](int32_t v) { return p->tensors[v].consumer >= 0 ? p->tensors[v].consumer + 1 : L; };
+      auto t_end = [&](int32_t v) {
+        int32_t e = p->tensors[v].consumer >= 0 ? p->tensors[v].consumer + 1 : L;
+        return std::max(e, keep_until[v] + 1);
+      };
       for (int32_t v = 0; v < L; ++v)
         p->tensors[v].off = place_block(live, p->tensors[v].bytes(), 0, t_end(v), high);
       for (int32_t k = 0; k + 1 < L; ++k) {
@@ -286,4 +459,19 @@ extern "C" void ltn_plan_free(ltn_plan* p) {
   if (!p) return;
   runtime_free(p);
   delete p;
+}
+
+extern "C" ltn_status ltn_plan_groups(const ltn_plan* p, int32_t* first_step, int32_t* n_steps,
+                                     int32_t* n_sigma, int32_t* work_rank, int32_t cap, int32_t* n) {
+  return guarded([&] {
+    require(p && n, "NULL argument");
+    require((int32_t)p->groups.size() <= cap || p->groups.empty(), "arrays too small", LTN_E_NOMEM);
+    for (size_t g = 0; g < p->groups.size(); ++g) {
+      if (first_step) first_step[g] = p->groups[g].st.front().step;
+      if (n_steps) n_steps[g] = (int32_t)p->groups[g].st.size();
+      if (n_sigma) n_sigma[g] = p->groups[g].nsig;
+      if (work_rank) work_rank[g] = p->groups[g].rmax;
+    }
+    *n = (int32_t)p->groups.size();
+  });
 }

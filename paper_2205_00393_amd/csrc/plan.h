@@ -48,6 +48,32 @@ struct StepPlan {
   uint64_t c_mask_a = 0;
 };
 
+// A fused sub-path (secondary slicing): consecutive stem steps s_1..s_L in
+// which the chain tensor T_{j-1} meets a small tensor Y_j and becomes T_j.
+// The indices of T_0 that survive to T_L are never touched inside, so fixing
+// them (Sigma: all of them except the earliest-contracted ones, which are
+// carried along to fill the working rank and to make writes contiguous)
+// splits the sub-path into 2^|Sigma| independent pieces; each works on
+// W_j = T_j without Sigma (at most 2^fuse_rank elements).
+constexpr int kMaxFuseStages = 16;
+struct FuseStage {
+  int32_t step = 0;
+  int32_t other = 0;        // SSA id of Y_j
+  int32_t m = 0, k = 0, n = 0;  // W_{j-1} = [2^m][2^k] rows, Y_j = [2^n][2^k]
+  uint64_t cmask = 0;       // positions in W_j of the bits from W_{j-1}
+};
+struct FuseGroup {
+  int32_t t0 = 0, tl = 0;   // SSA ids of T_0 and T_L
+  int32_t a = 0;            // low bits of T_0 that are not in Sigma
+  int32_t nsig = 0;         // |Sigma|
+  int32_t c = 0;            // rank of W_L
+  int32_t rmax = 0;         // largest W_j rank
+  int32_t b_elems = 0;      // sum of 2^rank(Y_j)
+  uint64_t sig_out = 0;     // positions of the Sigma bits in T_L
+  uint64_t w_out = 0;       // positions of the W_L bits in T_L
+  std::vector<FuseStage> st;
+};
+
 struct ltn_plan_impl;
 
 struct ltn_plan {
@@ -72,6 +98,8 @@ struct ltn_plan {
   ltn::BigSum macs;
   double macs_d = 0;
   ltn_options opt{};
+  std::vector<FuseGroup> groups;     // fused sub-paths (ltn_options.fuse_rank > 0)
+  std::vector<int32_t> step_group;   // per step: its group, or -1
   // device side (runtime)
   ltn_plan_impl* rt = nullptr;
 };

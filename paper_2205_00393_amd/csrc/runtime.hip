@@ -42,6 +42,7 @@ struct ltn_plan_impl {
   std::vector<GatherDesc> gd_fwd, gd_grad, gd_gcot;
   std::vector<ParamLeaf> pl;
   std::vector<int32_t> sl_bits, out_bits;
+  bool fuse = true;  // run fused sub-paths in forward passes
   // kernel choice per mode and step: kind 0 = generic (tk threads per
   // output), 1 = complex64 MFMA GEMM, 2 = split MFMA GEMM (cfg, swap),
   // 3 = narrow-step kernel (swap: rows taken from the B operand)
@@ -201,6 +202,42 @@ void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena, int mode) {
   }
 }
 
+// A fused sub-path at its last step (the plan keeps T_0 and the small
+// tensors live until then).
+void enqueue_group(ltn_plan* p, int g, int nb, int mode) {
+  auto& r = *p->rt;
+  const FuseGroup& G = p->groups[g];
+  FusedDesc d{};
+  d.X0 = arena_ptr(p, p->tensors[G.t0].off);
+  d.XL = arena_ptr(p, p->tensors[G.tl].off);
+  d.sX0 = int64_t(1) << p->tensors[G.t0].rank;
+  d.sXL = int64_t(1) << p->tensors[G.tl].rank;
+  d.a = G.a;
+  d.nsig = G.nsig;
+  d.c = G.c;
+  d.rmax = G.rmax;
+  d.nstages = (int32_t)G.st.size();
+  d.nb = nb;
+  d.sig_out = G.sig_out;
+  d.w_out = G.w_out;
+  if (mode == LTN_SPLIT_F16) d.scale_c = slot(p, G.tl);
+  int yoff = 0;
+  for (int j = 0; j < d.nstages; ++j) {
+    const FuseStage& s = G.st[j];
+    FusedStage& f = d.st[j];
+    f.Y = arena_ptr(p, p->tensors[s.other].off);
+    f.sY = int64_t(1) << p->tensors[s.other].rank;
+    f.m = s.m;
+    f.k = s.k;
+    f.n = s.n;
+    f.cmask = s.cmask;
+    f.yoff = yoff;
+    yoff += 1 << (s.k + s.n);
+  }
+  d.y_elems = yoff;
+  launch_fused(d, r.st);
+}
+
 void enqueue_forward(ltn_plan* p, int nb, bool gradarena, int mode) {
   auto& r = *p->rt;
   const GatherDesc* gd = reinterpret_cast<const GatherDesc*>(r.ws + (gradarena ? r.lay.gd_grad : r.lay.gd_fwd));
@@ -212,7 +249,14 @@ void enqueue_forward(ltn_plan* p, int nb, bool gradarena, int mode) {
   launch_gather(gd, (int)p->leaves.size(), r.max_leaf_elems,
                 reinterpret_cast<const float2*>(r.ws + r.lay.leafdata), arena_ptr(p, 0),
                 reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids), nb, scales, r.B, r.st);
-  for (int s = 0; s < (int)p->steps.size(); ++s) enqueue_step(p, s, nb, gradarena, mode);
+  for (int s = 0; s < (int)p->steps.size(); ++s) {
+    const int g = p->step_group[s];
+    if (g >= 0 && r.fuse && !gradarena) {
+      if (s == p->groups[g].st.back().step) enqueue_group(p, g, nb, mode);
+      continue;
+    }
+    enqueue_step(p, s, nb, gradarena, mode);
+  }
 }
 
 void enqueue_reduce(ltn_plan* p, int nb, bool gradarena, double* out) {
@@ -744,6 +788,14 @@ extern "C" ltn_status ltn_profile_steps(ltn_plan* p, uint64_t first, int32_t mod
     for (int s = 0; s < (int)p->steps.size(); ++s) HIPCHECK(hipEventElapsedTime(&ms_out[s], ev[s], ev[s + 1]));
     for (auto& e : ev) (void)hipEventDestroy(e);
     check_launch();
+  });
+}
+
+extern "C" ltn_status ltn_set_fusion(ltn_plan* p, int32_t enable) {
+  return guarded([&] {
+    require(p && p->rt, "plan is not bound", LTN_E_STATE);
+    drop_graphs(p);
+    p->rt->fuse = enable != 0;
   });
 }
 

@@ -29,12 +29,12 @@ def _stream_ptr(stream=None):
 
 class Plan:
     def __init__(self, net: Network, path, sliced: Sequence[int], max_rank: int = -1,
-                 batch: int = 0, fat_threshold: int = 0):
+                 batch: int = 0, fat_threshold: int = 0, fuse_rank: int = 0):
         self.net = net
         self.path = [tuple(p) for p in path]
         self.sliced = [int(x) for x in sliced]
         flat = [int(x) for p in self.path for x in p]
-        opt = L.Options(max_rank, batch, fat_threshold, 0)
+        opt = L.Options(max_rank, batch, fat_threshold, fuse_rank)
         h = C.c_void_p()
         L.check(L.lib().ltn_plan_load(C.byref(net.view), L.i32_array(flat), len(self.sliced),
                                       L.i32_array(self.sliced), C.byref(opt), C.byref(h)))
@@ -72,6 +72,17 @@ class Plan:
                     b_idx=[s.b_idx[j] for j in range(kb)],
                     c_idx=[s.c_idx[j] for j in range(s.m + s.n)], c_mask_a=s.c_mask_a,
                     arena_off=(s.arena_off_a, s.arena_off_b, s.arena_off_c))
+
+    def groups(self) -> List[dict]:
+        """Fused sub-paths: first step, number of steps, |Sigma|, working rank."""
+        cap = max(1, self.info()["n_steps"])
+        a, b, c, d = [(C.c_int32 * cap)() for _ in range(4)]
+        n = C.c_int32()
+        L.check(L.lib().ltn_plan_groups(self._h, a, b, c, d, cap, C.byref(n)))
+        return [dict(first_step=a[g], n_steps=b[g], n_sigma=c[g], work_rank=d[g]) for g in range(n.value)]
+
+    def set_fusion(self, enable: bool) -> None:
+        L.check(L.lib().ltn_set_fusion(self._h, 1 if enable else 0))
 
     def steps(self) -> List[dict]:
         return [self.step(k) for k in range(self.info()["n_steps"])]
