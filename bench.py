@@ -107,11 +107,11 @@ def main():
     w = make_workload(args.workload)
     ref = np.load(GOLDEN) if os.path.exists(GOLDEN) else None
 
-    def run_plan(pr, mode_list, tag):
+    def run_plan(pr, mode_list, tag, fuse_rank=0):
         """Bind a prepared plan and time each mode on it; returns (results,
         plan facts)."""
         t0 = time.perf_counter()
-        plan = pr.plan()
+        plan = pr.plan(fuse_rank=fuse_rank)
         costs = P.tree_costs(pr.net, pr.path, pr.sliced)
         t_plan = time.perf_counter() - t0 + pr_seconds[tag]
         if args.workload == "rqc30":
@@ -187,7 +187,8 @@ def main():
 
         results = {m: measure(m) for m in mode_list}
         facts = dict(n_slices=n_slices, batch=batch, costs=costs, macs_slice=macs_slice,
-                     flops_step=flops_step, n_sliced=len(pr.sliced), plan_seconds=t_plan)
+                     flops_step=flops_step, n_sliced=len(pr.sliced), plan_seconds=t_plan,
+                     groups=plan.groups())
         del plan
         torch.cuda.empty_cache()
         return results, facts
@@ -205,11 +206,10 @@ def main():
     variant = None
     if args.path_variant:
         t0 = time.perf_counter()
-        prv = P.prepare(w, reconf_k=8, refine_seeds=2 if args.workload == "rqc53" else 0)
+        prv = P.prepare(w, reconf_k=8)
         pr_seconds["reconf"] = time.perf_counter() - t0
         vres, vf = run_plan(prv, args.path_variant.split(","), "reconf")
-        variant = {"path": "randomised greedy + subtree reconfiguration (k=8)" +
-                   (" + slice refiner" if args.workload == "rqc53" else ""),
+        variant = {"path": "randomised greedy + subtree reconfiguration (k=8)",
                    "plan_seconds": round(vf["plan_seconds"], 3),
                    "sliced_indices": vf["n_sliced"], "log2_C_BS": round(vf["costs"].log2_sliced, 4),
                    "overhead": round(vf["costs"].overhead, 5), "macs_per_slice": vf["macs_slice"],
@@ -217,6 +217,14 @@ def main():
                                                     for m, r in vres.items()},
                    "modes": {m: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
                              for m, r in vres.items()}}
+        if args.workload == "rqc30":
+            # the same path with fused sub-paths (secondary slicing, working rank 11)
+            pr_seconds["reconf+fused"] = pr_seconds["reconf"]
+            fres, ff = run_plan(prv, ["c64"], "reconf+fused", fuse_rank=11)
+            variant["fused_sub_paths"] = {
+                "fuse_rank": 11, "groups": len(ff["groups"]),
+                "steps_fused": sum(g["n_steps"] for g in ff["groups"]),
+                "c64": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in fres["c64"].items()}}
         for m, r in vres.items():
             if m in results:
                 variant["modes"][m]["time_to_solution_speedup_vs_greedy_path"] = round(
