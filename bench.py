@@ -37,6 +37,11 @@ def counter_traffic(mode):
     return rec["traffic_bytes_per_launch"]
 
 
+def sig6(v):
+    """Six significant digits (small errors stay visible)."""
+    return float(f"{v:.6g}") if isinstance(v, float) else v
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -215,8 +220,7 @@ def main():
                    "overhead": round(vf["costs"].overhead, 5), "macs_per_slice": vf["macs_slice"],
                    "projected_seconds_all_slices": {m: r["sec_per_slice"] * 2.0 ** vf["n_sliced"]
                                                     for m, r in vres.items()},
-                   "modes": {m: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
-                             for m, r in vres.items()}}
+                   "modes": {m: {k: sig6(v) for k, v in r.items()} for m, r in vres.items()}}
         if args.workload == "rqc30":
             # the same path with fused sub-paths (secondary slicing, working rank 11)
             pr_seconds["reconf+fused"] = pr_seconds["reconf"]
@@ -224,7 +228,7 @@ def main():
             variant["fused_sub_paths"] = {
                 "fuse_rank": 11, "groups": len(ff["groups"]),
                 "steps_fused": sum(g["n_steps"] for g in ff["groups"]),
-                "c64": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in fres["c64"].items()}}
+                "c64": {k: sig6(v) for k, v in fres["c64"].items()}}
         for m, r in vres.items():
             if m in results:
                 variant["modes"][m]["time_to_solution_speedup_vs_greedy_path"] = round(
@@ -247,7 +251,7 @@ def main():
                 "share_of_step_time": round(r0["mfma_ms_per_batch"] / r0["step_ms_per_batch"], 4)}
     modes = {}
     for m, r in results.items():
-        modes[m] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
+        modes[m] = {k: sig6(v) for k, v in r.items()}
         modes[m]["speedup_vs_c64"] = round(r["tflops"] / results["c64"]["tflops"], 4) if "c64" in results else None
         modes[m]["meets_tolerance"] = (r.get("rel_l2_error") is not None and
                                        r["rel_l2_error"] <= (1e-4 if m == "c64" else 5e-4))
