@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--workload", default="rqc30", choices=["rqc30", "rqc53"],
                     help="rqc30: every slice per step; rqc53: a seeded sample of --slices slices")
     ap.add_argument("--slices", type=int, default=8, help="rqc53: sampled slices per step")
+    ap.add_argument("--path", default="greedy", choices=["greedy", "reconf"],
+                    help="path of the headline plan: randomised greedy (the workload's definition) "
+                         "or greedy + subtree reconfiguration")
     ap.add_argument("--path-variant", default="c64,split_bf16",
                     help="modes to time on the reconfigured path as well ('' to skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -200,16 +203,16 @@ def main():
 
     pr_seconds = {}
     t0 = time.perf_counter()
-    pr = P.prepare(w)
-    pr_seconds["greedy"] = time.perf_counter() - t0
-    results, facts = run_plan(pr, args.modes.split(","), "greedy")
+    pr = P.prepare(w, reconf_k=8 if args.path == "reconf" else 0)
+    pr_seconds[args.path] = time.perf_counter() - t0
+    results, facts = run_plan(pr, args.modes.split(","), args.path)
     n_slices, batch, costs = facts["n_slices"], facts["batch"], facts["costs"]
     macs_slice, flops_step = facts["macs_slice"], facts["flops_step"]
 
     # the same workload on a better path: greedy trials improved by subtree
     # reconfiguration (and, for the 53-qubit case, a refined slicing set)
     variant = None
-    if args.path_variant:
+    if args.path_variant and args.path == "greedy":
         t0 = time.perf_counter()
         prv = P.prepare(w, reconf_k=8)
         pr_seconds["reconf"] = time.perf_counter() - t0
@@ -284,7 +287,7 @@ def main():
                    "slices": n_slices, "sliced_indices": len(pr.sliced), "batch": batch,
                    "log2_C_BS": round(costs.log2_sliced, 4), "overhead": round(costs.overhead, 5),
                    "macs_per_slice": macs_slice, "flops_per_step": flops_step,
-                   "mode": main_mode},
+                   "mode": main_mode, "path": args.path},
         "sec_per_slice": r0["sec_per_slice"],
         "rel_l2_error": err,
         "modes": modes,
