@@ -70,6 +70,47 @@ def cpu_baseline(budget_s=30.0):
                       "numpy complex128 tensordot along the oracle's own path"}
 
 
+def gradient_leg(torch, P, args):
+    """Forward + adjoint of the 20-qubit u3 workload (720 angles, loss over
+    256 bitstrings, each one slice), timed with the same warm-up / step
+    counts, checked against the stored oracle adjoint gradient."""
+    from paper_2205_00393_amd.autograd import Amplitudes
+    from workload import make_workload
+    w = make_workload("rqc20_grad")
+    pr = P.prepare(w, alphas=(0.5, 1.0), taus=(0.0, 0.3), n_seeds=3)
+    plan = pr.plan()
+    batch = plan.bind(batch=0, grad=True, budget_bytes=8 << 30)
+    ids = [pr.slice_of_bitstring(int(x)) for x in w.bitstrings]
+    sel = torch.as_tensor(np.asarray(w.bitstrings), device="cuda")
+    angles0 = torch.tensor(w.circuit.angles(), dtype=torch.float64, device="cuda")
+
+    def step():
+        angles = angles0.clone().requires_grad_(True)
+        out = Amplitudes.apply(angles, plan, ids)
+        loss = torch.sum(torch.log(torch.abs(out[sel]) ** 2))
+        loss.backward()
+        return angles.grad
+    for _ in range(max(1, args.warmup)):
+        g = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    res = {"workload": "rqc20_grad: 4x5 grid, 12 cycles, u3 gates (720 angles), "
+                       "loss over 256 bitstrings (one slice each)",
+           "batch": batch, "ms_fwd_bwd": sig6(dt * 1e3),
+           "ms_per_bitstring": sig6(dt * 1e3 / len(ids))}
+    ref_path = os.path.join(ROOT, "tests", "golden", "rqc20_grad_reference.npz")
+    if os.path.exists(ref_path):
+        ref = np.load(ref_path)
+        gg = g.detach().cpu().numpy()
+        res["grad_rel_l2_error"] = sig6(float(np.linalg.norm(gg - ref["grad"]) / np.linalg.norm(ref["grad"])))
+    log(f"gradient: {res['ms_fwd_bwd']:.2f} ms forward + backward, error {res.get('grad_rel_l2_error')}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +128,8 @@ def main():
                          "or greedy + subtree reconfiguration")
     ap.add_argument("--path-variant", default="c64,split_bf16",
                     help="modes to time on the reconfigured path as well ('' to skip)")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="skip the gradient leg (20-qubit, 720 angles, 256 bitstrings)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -259,6 +302,10 @@ def main():
         modes[m]["meets_tolerance"] = (r.get("rel_l2_error") is not None and
                                        r["rel_l2_error"] <= (1e-4 if m == "c64" else 5e-4))
 
+    grad = None
+    if not args.no_grad and args.workload == "rqc30":
+        grad = gradient_leg(torch, P, args)
+
     cpu = None
     if not args.no_cpu and args.workload == "rqc30":
         log("timing the CPU oracle on one slice ...")
@@ -294,6 +341,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "path_variant": variant,
+        "gradient": grad,
     }
     print(json.dumps(line), flush=True)
 

@@ -1,5 +1,7 @@
 // Bit permutation of a batch of complex64 tensors:
-//     out[b][y] = in[b][x],  bit perm[j] of y = bit j of x.
+//     out[b][y] = in[b][x],  bit perm[j] of y = bit j of x
+// (optionally conjugated on the way: the sign bit of the imaginary part is
+// flipped).
 // Each block moves one tile: the source bits T = the lowest 5 source bits
 // plus the source bits that land on the lowest 5 destination bits, filled
 // up with the next source bits to 12; the other bits are fixed per block. The tile is read in source order
@@ -88,7 +90,7 @@ __global__ __launch_bounds__(kThreads) void k_permute(const uint64_t* __restrict
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kPer; ++i)
-      if (tid + kThreads * i < nt) v[i] = tile[rslot[i]];
+      if (tid + kThreads * i < nt) v[i] = tile[rslot[i]] ^ d.flip;
 #pragma unroll
     for (int i = 0; i < kPer; ++i)
       if (tid + kThreads * i < nt) __builtin_nontemporal_store(v[i], &dst[doff[i]]);

@@ -96,6 +96,7 @@ struct GemmDesc {
 struct PermuteDesc {
   int32_t rank, n_tile, n_outer;
   int64_t batch;
+  uint64_t flip;         // XORed into every element (1 << 63: complex conjugate)
   int8_t tile_src[16];   // tile bit k -> source bit (ascending)
   int8_t tile_dst[16];   // destination-order rank r -> destination bit
   int8_t dst_tile[16];   // destination-order rank r -> tile bit

@@ -26,7 +26,8 @@ using namespace ltn;
   } while (0)
 
 struct Layout {
-  size_t leafdata, gd_fwd, gd_grad, gd_gcot, pl, angles, leafgrad, ids, scales, arena, split, total;
+  size_t leafdata, gd_fwd, gd_grad, gd_gcot, pl, angles, leafgrad, ids, scales, arena, split, gscr,
+      gscr_c, total;
 };
 
 struct ltn_plan_impl {
@@ -87,6 +88,17 @@ Layout layout(const ltn_plan* p, int B, int grad) {
   o = al(o + (size_t)B * (grad ? p->garena : p->arena));
   l.split = o;
   o = al(o + (size_t)B * p->split_scratch);
+  // adjoint scratch: a permuted copy of an output cotangent and of one operand
+  size_t sc = 0, so = 0;
+  if (grad)
+    for (auto& sp : p->steps) {
+      sc = std::max<size_t>(sc, p->tensors[sp.out].bytes());
+      so = std::max<size_t>(so, std::max(p->tensors[sp.a].bytes(), p->tensors[sp.b].bytes()));
+    }
+  l.gscr = o;
+  o = al(o + (size_t)B * so);
+  l.gscr_c = o;
+  o = al(o + (size_t)B * sc);
   l.total = o;
   return l;
 }
@@ -509,6 +521,89 @@ extern "C" ltn_status ltn_set_params(ltn_plan* p, const double* d_angles) {
   });
 }
 
+// One adjoint product in the forward form: C[merge(m, n)] = sum_k
+// X[m 2^k + k] Y[n 2^k + k] over a batch of nb slices, on the complex64
+// MFMA GEMM when a tile fits (either operand role), else the narrow kernel,
+// else the generic kernel.
+static void enqueue_nt(ltn_plan* p, const float2* X, int64_t sX, const float2* Y, int64_t sY,
+                       float2* C, int64_t sC, int m, int k, int n, uint64_t cmask, int nb) {
+  auto& r = *p->rt;
+  const uint64_t full = (m + n) >= 64 ? ~0ull : ((1ull << (m + n)) - 1);
+  for (int sw = 0; sw < 2; ++sw) {
+    const int mm = sw ? n : m, nn = sw ? m : n;
+    const int cfg = default_cfg(mm, k, nn, LTN_C64);
+    if (cfg >= 0 && mm >= 5 && nn >= 5) {
+      GemmDesc d{};
+      d.A = sw ? Y : X;
+      d.B = sw ? X : Y;
+      d.C = C;
+      d.sA = sw ? sY : sX;
+      d.sB = sw ? sX : sY;
+      d.sC = sC;
+      d.m = mm;
+      d.n = nn;
+      d.k = k;
+      d.cmask = sw ? (~cmask & full) : cmask;
+      d.nb = nb;
+      d.cfg = cfg;
+      launch_cgemm(d, LTN_C64, r.st);
+      return;
+    }
+  }
+  if (m + n >= 12) {
+    const bool sw = n > m;
+    if (sw ? narrow_fits(n, k, m) : narrow_fits(m, k, n)) {
+      NarrowDesc d{};
+      d.A = sw ? Y : X;
+      d.B = sw ? X : Y;
+      d.C = C;
+      d.sA = sw ? sY : sX;
+      d.sB = sw ? sX : sY;
+      d.sC = sC;
+      d.m = sw ? n : m;
+      d.n = sw ? m : n;
+      d.k = k;
+      d.cmask = sw ? (~cmask & full) : cmask;
+      d.nb = nb;
+      launch_narrow(d, r.st);
+      return;
+    }
+  }
+  GenericDesc g{};
+  g.P = X;
+  g.Q = Y;
+  g.out = C;
+  g.sP = sX;
+  g.sQ = sY;
+  g.sO = sC;
+  g.xb = m;
+  g.yb = n;
+  g.zb = k;
+  g.px = ((1ull << m) - 1) << k;
+  g.pz = (1ull << k) - 1;
+  g.qy = ((1ull << n) - 1) << k;
+  g.qz = (1ull << k) - 1;
+  g.ox = cmask;
+  g.oy = ~cmask & full;
+  g.nb = nb;
+  launch_generic(g, default_tk(k, (1ull << (m + n)) * (uint64_t)nb), r.st);
+}
+
+static PermuteDesc plan_permute(int32_t rank, const int32_t* perm, int64_t batch, bool conj);
+
+// Bit permutation of a batch of nb tensors (slice stride 2^rank), optionally
+// conjugated, into `out`; returns the tensor to read (the input itself for
+// the identity without conjugation).
+static const float2* enqueue_perm(ltn_plan* p, const float2* in, float2* out,
+                                  const std::vector<int32_t>& perm, int nb, bool conj) {
+  bool ident = !conj;
+  for (size_t j = 0; j < perm.size() && ident; ++j) ident = perm[j] == (int32_t)j;
+  if (ident) return in;
+  PermuteDesc d = plan_permute((int32_t)perm.size(), perm.data(), nb, conj);
+  launch_permute(in, out, d, p->rt->st);
+  return out;
+}
+
 extern "C" ltn_status ltn_execute_grad(ltn_plan* p, const uint64_t* ids, uint64_t n, int32_t mode,
                                        const void* d_cot, void* d_out, double* d_angle_grad) {
   return guarded([&] {
@@ -538,48 +633,87 @@ extern "C" ltn_status ltn_execute_grad(ltn_plan* p, const uint64_t* ids, uint64_
         const StepPlan& sp = p->steps[s];
         if (!r.needs_grad[sp.out]) continue;
         const TensorPlan &ta = p->tensors[sp.a], &tb = p->tensors[sp.b], &tc = p->tensors[sp.out];
-        const uint64_t cm = sp.c_mask_a, full = (1ull << (sp.m + sp.n)) - 1;
+        const uint64_t cm = sp.c_mask_a;
+        // small steps: one generic kernel per operand, reading the operands
+        // in place (strided) and conjugating the second one
+        if (sp.m + sp.n + sp.k <= 16) {
+          const uint64_t full = (1ull << (sp.m + sp.n)) - 1;
+          if (r.needs_grad[sp.a]) {
+            GenericDesc g{};
+            g.P = arena_ptr(p, tc.gcot);
+            g.Q = arena_ptr(p, tb.goff);
+            g.out = arena_ptr(p, ta.gcot);
+            g.sP = int64_t(1) << tc.rank;
+            g.sQ = int64_t(1) << tb.rank;
+            g.sO = int64_t(1) << ta.rank;
+            g.xb = sp.m;
+            g.yb = sp.k;
+            g.zb = sp.n;
+            g.px = cm;
+            g.pz = ~cm & full;
+            g.qy = (1ull << sp.k) - 1;
+            g.qz = ((1ull << sp.n) - 1) << sp.k;
+            g.ox = ((1ull << sp.m) - 1) << sp.k;
+            g.oy = (1ull << sp.k) - 1;
+            g.conjQ = 1;
+            g.nb = nb;
+            launch_generic(g, default_tk(sp.n, (1ull << (sp.m + sp.k)) * (uint64_t)nb), r.st);
+          }
+          if (r.needs_grad[sp.b]) {
+            GenericDesc g{};
+            g.P = arena_ptr(p, tc.gcot);
+            g.Q = arena_ptr(p, ta.goff);
+            g.out = arena_ptr(p, tb.gcot);
+            g.sP = int64_t(1) << tc.rank;
+            g.sQ = int64_t(1) << ta.rank;
+            g.sO = int64_t(1) << tb.rank;
+            g.xb = sp.n;
+            g.yb = sp.k;
+            g.zb = sp.m;
+            g.px = ~cm & full;
+            g.pz = cm;
+            g.qy = (1ull << sp.k) - 1;
+            g.qz = ((1ull << sp.m) - 1) << sp.k;
+            g.ox = ((1ull << sp.n) - 1) << sp.k;
+            g.oy = (1ull << sp.k) - 1;
+            g.conjQ = 1;
+            g.nb = nb;
+            launch_generic(g, default_tk(sp.m, (1ull << (sp.n + sp.k)) * (uint64_t)nb), r.st);
+          }
+          continue;
+        }
+        // adjoint products in the forward form: the output cotangent
+        // and the other operand are permuted so that the summed bits are
+        // lowest (and the operand conjugated), then one GEMM per operand
+        float2* Xs = reinterpret_cast<float2*>(r.ws + r.lay.gscr_c);
+        float2* Ys = reinterpret_cast<float2*>(r.ws + r.lay.gscr);
+        const int rc = sp.m + sp.n;
+        // positions of the m bits (in order) and the n bits of the output
+        std::vector<int> mpos, npos;
+        for (int j = 0; j < rc; ++j) ((cm >> j) & 1 ? mpos : npos).push_back(j);
         if (r.needs_grad[sp.a]) {
-          GenericDesc g{};
-          g.P = arena_ptr(p, tc.gcot);
-          g.Q = arena_ptr(p, tb.goff);
-          g.out = arena_ptr(p, ta.gcot);
-          g.sP = int64_t(1) << tc.rank;
-          g.sQ = int64_t(1) << tb.rank;
-          g.sO = int64_t(1) << ta.rank;
-          g.xb = sp.m;
-          g.yb = sp.k;
-          g.zb = sp.n;
-          g.px = cm;
-          g.pz = ~cm & full;
-          g.qy = (1ull << sp.k) - 1;
-          g.qz = ((1ull << sp.n) - 1) << sp.k;
-          g.ox = ((1ull << sp.m) - 1) << sp.k;
-          g.oy = (1ull << sp.k) - 1;
-          g.conjQ = 1;
-          g.nb = nb;
-          launch_generic(g, default_tk(sp.n, (1ull << (sp.m + sp.k)) * (uint64_t)nb), r.st);
+          // dA[m][k] = sum_n dC[merge(m, n)] conj(B[n][k])
+          std::vector<int32_t> pc(rc), pb(sp.k + sp.n);
+          for (int i = 0; i < sp.m; ++i) pc[mpos[i]] = sp.n + i;
+          for (int i = 0; i < sp.n; ++i) pc[npos[i]] = i;
+          for (int j = 0; j < sp.k; ++j) pb[j] = sp.n + j;
+          for (int i = 0; i < sp.n; ++i) pb[sp.k + i] = i;
+          const float2* X = enqueue_perm(p, arena_ptr(p, tc.gcot), Xs, pc, nb, false);
+          enqueue_perm(p, arena_ptr(p, tb.goff), Ys, pb, nb, true);
+          enqueue_nt(p, X, int64_t(1) << rc, Ys, int64_t(1) << tb.rank, arena_ptr(p, ta.gcot),
+                     int64_t(1) << ta.rank, sp.m, sp.n, sp.k, ((1ull << sp.m) - 1) << sp.k, nb);
         }
         if (r.needs_grad[sp.b]) {
-          GenericDesc g{};
-          g.P = arena_ptr(p, tc.gcot);
-          g.Q = arena_ptr(p, ta.goff);
-          g.out = arena_ptr(p, tb.gcot);
-          g.sP = int64_t(1) << tc.rank;
-          g.sQ = int64_t(1) << ta.rank;
-          g.sO = int64_t(1) << tb.rank;
-          g.xb = sp.n;
-          g.yb = sp.k;
-          g.zb = sp.m;
-          g.px = ~cm & full;
-          g.pz = cm;
-          g.qy = (1ull << sp.k) - 1;
-          g.qz = ((1ull << sp.m) - 1) << sp.k;
-          g.ox = ((1ull << sp.n) - 1) << sp.k;
-          g.oy = (1ull << sp.k) - 1;
-          g.conjQ = 1;
-          g.nb = nb;
-          launch_generic(g, default_tk(sp.m, (1ull << (sp.n + sp.k)) * (uint64_t)nb), r.st);
+          // dB[n][k] = sum_m dC[merge(m, n)] conj(A[m][k])
+          std::vector<int32_t> pc(rc), pa(sp.k + sp.m);
+          for (int i = 0; i < sp.m; ++i) pc[mpos[i]] = i;
+          for (int i = 0; i < sp.n; ++i) pc[npos[i]] = sp.m + i;
+          for (int j = 0; j < sp.k; ++j) pa[j] = sp.m + j;
+          for (int i = 0; i < sp.m; ++i) pa[sp.k + i] = i;
+          const float2* X = enqueue_perm(p, arena_ptr(p, tc.gcot), Xs, pc, nb, false);
+          enqueue_perm(p, arena_ptr(p, ta.goff), Ys, pa, nb, true);
+          enqueue_nt(p, X, int64_t(1) << rc, Ys, int64_t(1) << ta.rank, arena_ptr(p, tb.gcot),
+                     int64_t(1) << tb.rank, sp.n, sp.m, sp.k, ((1ull << sp.n) - 1) << sp.k, nb);
         }
       }
       launch_leaf_cot_accumulate(reinterpret_cast<const ParamLeaf*>(r.ws + r.lay.pl), r.n_pl, gcot,
@@ -846,6 +980,67 @@ extern "C" ltn_status ltn_step_kernel(const ltn_plan* p, int32_t step, int32_t m
   });
 }
 
+// Tile plan of a bit permutation (see k_permute): the tile holds the lowest
+// 5 source bits, the sources of the lowest 5 destination bits and then the
+// next source bits up to 12; the LDS swizzle spreads one half-wave's reads
+// in destination order over distinct banks.
+static PermuteDesc plan_permute(int32_t rank, const int32_t* perm, int64_t batch, bool conj) {
+  std::vector<int> inv(rank, -1);
+  for (int j = 0; j < rank; ++j) {
+    require(perm[j] >= 0 && perm[j] < rank && inv[perm[j]] < 0, "perm is not a permutation");
+    inv[perm[j]] = j;
+  }
+  PermuteDesc d{};
+  d.rank = rank;
+  d.batch = batch;
+  const int t = std::min(rank, 5);
+  std::vector<char> in_tile(rank, 0);
+  for (int j = 0; j < t; ++j) in_tile[j] = 1;          // lowest source bits
+  for (int y = 0; y < t; ++y) in_tile[inv[y]] = 1;     // sources of the lowest destination bits
+  int nt = 0;
+  for (int j = 0; j < rank; ++j) nt += in_tile[j];
+  for (int j = 0; j < rank && nt < std::min(rank, 12); ++j)
+    if (!in_tile[j]) {
+      in_tile[j] = 1;  // fill the tile up to 4096 elements with the next source bits
+      ++nt;
+    }
+  std::vector<int> tsrc, outer;
+  for (int j = 0; j < rank; ++j) (in_tile[j] ? tsrc : outer).push_back(j);
+  d.n_tile = (int)tsrc.size();
+  d.n_outer = (int)outer.size();
+  for (int k = 0; k < d.n_tile; ++k) d.tile_src[k] = (int8_t)tsrc[k];
+  // destination order of the tile bits
+  std::vector<std::pair<int, int>> dt;
+  for (int k = 0; k < d.n_tile; ++k) dt.push_back({perm[tsrc[k]], k});
+  std::sort(dt.begin(), dt.end());
+  for (int r = 0; r < d.n_tile; ++r) {
+    d.tile_dst[r] = (int8_t)dt[r].first;
+    d.dst_tile[r] = (int8_t)dt[r].second;
+  }
+  for (int k = 0; k < d.n_outer; ++k) {
+    d.outer_src[k] = (int8_t)outer[k];
+    d.outer_dst[k] = (int8_t)perm[outer[k]];
+  }
+  // LDS swizzle: the tile bits read by one half-wave in destination order
+  // are dst_tile[0..4]; those at tile bit >= 5 each get a distinct low bit
+  // not already among them, so the 32 slots differ in their low 5 bits.
+  {
+    const int nr = std::min(d.n_tile, 5);
+    bool used[5] = {false, false, false, false, false};
+    for (int r = 0; r < nr; ++r)
+      if (d.dst_tile[r] < 5) used[d.dst_tile[r]] = true;
+    int next = 0;
+    for (int r = 0; r < nr; ++r)
+      if (d.dst_tile[r] >= 5) {
+        while (used[next]) ++next;
+        used[next] = true;
+        d.swz[d.dst_tile[r] - 5] = (uint8_t)(1u << next);
+      }
+  }
+  d.flip = conj ? (1ull << 63) : 0;
+  return d;
+}
+
 extern "C" ltn_status ltn_permute(const void* d_in, void* d_out, int32_t rank, const int32_t* perm,
                                   int64_t batch, void* stream) {
   return guarded([&] {
@@ -854,58 +1049,13 @@ extern "C" ltn_status ltn_permute(const void* d_in, void* d_out, int32_t rank, c
     require(rank >= 0 && rank <= 40, "rank must be in 0..40");
     require(batch >= 1, "batch must be >= 1");
     require(rank == 0 || perm != nullptr, "perm is NULL");
-    std::vector<int> inv(rank, -1);
+    for (int j = 0; j < rank; ++j) require(perm[j] >= 0 && perm[j] < rank, "perm is not a permutation");
+    std::vector<char> seen(rank, 0);
     for (int j = 0; j < rank; ++j) {
-      require(perm[j] >= 0 && perm[j] < rank && inv[perm[j]] < 0, "perm is not a permutation");
-      inv[perm[j]] = j;
+      require(!seen[perm[j]], "perm is not a permutation");
+      seen[perm[j]] = 1;
     }
-    PermuteDesc d{};
-    d.rank = rank;
-    d.batch = batch;
-    const int t = std::min(rank, 5);
-    std::vector<char> in_tile(rank, 0);
-    for (int j = 0; j < t; ++j) in_tile[j] = 1;          // lowest source bits
-    for (int y = 0; y < t; ++y) in_tile[inv[y]] = 1;     // sources of the lowest destination bits
-    int nt = 0;
-    for (int j = 0; j < rank; ++j) nt += in_tile[j];
-    for (int j = 0; j < rank && nt < std::min(rank, 12); ++j)
-      if (!in_tile[j]) {
-        in_tile[j] = 1;  // fill the tile up to 4096 elements with the next source bits
-        ++nt;
-      }
-    std::vector<int> tsrc, outer;
-    for (int j = 0; j < rank; ++j) (in_tile[j] ? tsrc : outer).push_back(j);
-    d.n_tile = (int)tsrc.size();
-    d.n_outer = (int)outer.size();
-    for (int k = 0; k < d.n_tile; ++k) d.tile_src[k] = (int8_t)tsrc[k];
-    // destination order of the tile bits
-    std::vector<std::pair<int, int>> dt;
-    for (int k = 0; k < d.n_tile; ++k) dt.push_back({perm[tsrc[k]], k});
-    std::sort(dt.begin(), dt.end());
-    for (int r = 0; r < d.n_tile; ++r) {
-      d.tile_dst[r] = (int8_t)dt[r].first;
-      d.dst_tile[r] = (int8_t)dt[r].second;
-    }
-    for (int k = 0; k < d.n_outer; ++k) {
-      d.outer_src[k] = (int8_t)outer[k];
-      d.outer_dst[k] = (int8_t)perm[outer[k]];
-    }
-    // LDS swizzle: the tile bits read by one half-wave in destination order
-    // are dst_tile[0..4]; those at tile bit >= 5 each get a distinct low bit
-    // not already among them, so the 32 slots differ in their low 5 bits.
-    {
-      const int nr = std::min(d.n_tile, 5);
-      bool used[5] = {false, false, false, false, false};
-      for (int r = 0; r < nr; ++r)
-        if (d.dst_tile[r] < 5) used[d.dst_tile[r]] = true;
-      int next = 0;
-      for (int r = 0; r < nr; ++r)
-        if (d.dst_tile[r] >= 5) {
-          while (used[next]) ++next;
-          used[next] = true;
-          d.swz[d.dst_tile[r] - 5] = (uint8_t)(1u << next);
-        }
-    }
+    PermuteDesc d = plan_permute(rank, perm, batch, false);
     launch_permute(reinterpret_cast<const float2*>(d_in), reinterpret_cast<float2*>(d_out), d,
                    reinterpret_cast<hipStream_t>(stream));
     check_launch();
