@@ -319,11 +319,11 @@ struct SplitCfg {
   static_assert(TM >= 1 && TN >= 1 && BKC % 8 == 0, "tile too small for the split GEMM");
 };
 
-// Two waves per SIMD where the registers allow it without spilling (the
+// Two or three waves per SIMD where the registers allow it without spilling (the
 // accumulators then live in VGPRs), so that one block's LDS staging and
 // barriers overlap another block's matrix work.
 template <int BM, int BNC, int BKC, bool BF>
-__global__ __launch_bounds__(256, (BM * BNC >= 16384 && BKC >= 32) ? 1 : 2) void k_cgemm_split(GemmDesc d) {
+__global__ __launch_bounds__(256, (BM * BNC >= 16384 && BKC >= 32) ? 1 : (BM * BNC >= 16384 || BKC >= 32 ? 2 : 3)) void k_cgemm_split(GemmDesc d) {
   using C = SplitCfg<BM, BNC, BKC>;
   // LDS rows of U 16-byte units (one unit = 4 complex of hi or lo parts);
   // row r starts at unit U r + r / (16 / U), so that 16 consecutive rows at
