@@ -32,7 +32,9 @@ __device__ __forceinline__ uint64_t spread(uint64_t v, const int8_t* pos, int n)
 // destination order fall into 32 distinct bank pairs.
 constexpr int kThreads = 256, kPer = (1 << kTileBits) / kThreads;
 
-// Elements are moved as 64-bit words (pure data movement, bit-exact).
+// Elements are moved as 64-bit words (pure data movement, bit-exact); the
+// conjugating variant flips the sign bit of each imaginary part.
+template <bool CONJ>
 __global__ __launch_bounds__(kThreads) void k_permute(const uint64_t* __restrict__ in,
                                                       uint64_t* __restrict__ out, PermuteDesc d) {
   __shared__ uint64_t tile[1 << kTileBits];
@@ -90,7 +92,7 @@ __global__ __launch_bounds__(kThreads) void k_permute(const uint64_t* __restrict
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kPer; ++i)
-      if (tid + kThreads * i < nt) v[i] = tile[rslot[i]] ^ d.flip;
+      if (tid + kThreads * i < nt) v[i] = CONJ ? (tile[rslot[i]] ^ (1ull << 63)) : tile[rslot[i]];
 #pragma unroll
     for (int i = 0; i < kPer; ++i)
       if (tid + kThreads * i < nt) __builtin_nontemporal_store(v[i], &dst[doff[i]]);
@@ -103,8 +105,12 @@ __global__ __launch_bounds__(kThreads) void k_permute(const uint64_t* __restrict
 void launch_permute(const float2* in, float2* out, const PermuteDesc& d, hipStream_t st) {
   int64_t blocks = (int64_t(1) << d.n_outer) * d.batch;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_permute, dim3((unsigned)blocks), dim3(kThreads), 0, st, reinterpret_cast<const uint64_t*>(in),
-                     reinterpret_cast<uint64_t*>(out), d);
+  if (d.flip)
+    hipLaunchKernelGGL(k_permute<true>, dim3((unsigned)blocks), dim3(kThreads), 0, st,
+                       reinterpret_cast<const uint64_t*>(in), reinterpret_cast<uint64_t*>(out), d);
+  else
+    hipLaunchKernelGGL(k_permute<false>, dim3((unsigned)blocks), dim3(kThreads), 0, st,
+                       reinterpret_cast<const uint64_t*>(in), reinterpret_cast<uint64_t*>(out), d);
 }
 
 }  // namespace ltn
