@@ -9,8 +9,12 @@ sub-slice indices are summed over; sliced open indices are placed).
 Stores, per slice, 4096 amplitudes at seeded output positions (seed 5) and
 the squared norm of the whole 2^20-amplitude block.
 
-Usage: python tests/golden/make_rqc53_reference.py [N] [OUTDIR]
+Usage: python tests/golden/make_rqc53_reference.py [N] [OUTDIR] [--reconf K]
 Needs ~60 GiB of host memory and minutes per slice on 16 cores.
+
+With --reconf K every greedy trial is improved by the oracle's subtree
+reconfiguration (frontiers of K tensors, 4 sweeps) as in the library's
+search, and the files are named rqc53_reconf_slices.*.
 """
 import hashlib
 import json
@@ -33,12 +37,18 @@ N_POS = 4096
 
 
 def main():
-    n_slices = int(sys.argv[1]) if len(sys.argv) > 1 else 1
-    outdir = sys.argv[2] if len(sys.argv) > 2 else HERE
+    args = [a for a in sys.argv[1:] if not a.startswith("--")]
+    reconf = 0
+    if "--reconf" in sys.argv:
+        reconf = int(sys.argv[sys.argv.index("--reconf") + 1])
+        args = [a for a in args if a != str(reconf)]
+    n_slices = int(args[0]) if len(args) > 0 else 1
+    outdir = args[1] if len(args) > 1 else HERE
     w = make_workload("rqc53")
     net = nw.absorb_small(nw.circuit_network(w.circuit, w.open_qubits, w.closed_bits))
     t0 = time.time()
-    path, S, trial = pl.path_search(net.indices, w.max_rank, (), ALPHAS, TAUS, SEEDS)
+    path, S, trial = pl.path_search(net.indices, w.max_rank, (), ALPHAS, TAUS, SEEDS,
+                                    reconf_k=reconf, reconf_sweeps=4)
     tree = pl.Tree(net.indices, path)
     print(f"path search {time.time() - t0:.1f}s trial {trial} |S|={len(S)}", flush=True)
     S2 = pl.slice_finder(tree, T_SUB, pre=S)
@@ -60,8 +70,10 @@ def main():
             print(f"slice {s} sub-slice {e} {time.time() - t1:.1f}s", flush=True)
         rec["slices"].append(dict(id=str(s), norm2=float(np.sum(np.abs(out) ** 2))))
         amps.append(out[pos])
-    np.savez(os.path.join(outdir, "rqc53_slices.npz"), positions=pos, amplitudes=np.asarray(amps))
-    json.dump(rec, open(os.path.join(outdir, "rqc53_slices.json"), "w"), indent=1)
+    stem = "rqc53_reconf_slices" if reconf else "rqc53_slices"
+    rec["reconf_k"] = reconf
+    np.savez(os.path.join(outdir, stem + ".npz"), positions=pos, amplitudes=np.asarray(amps))
+    json.dump(rec, open(os.path.join(outdir, stem + ".json"), "w"), indent=1)
     print(json.dumps(rec)[:400], flush=True)
 
 

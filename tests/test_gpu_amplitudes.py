@@ -279,3 +279,32 @@ def test_rqc53_sampled_slice(torch):
         banner(f"rqc53 slice {s}: sampled rel err {err:.3e}, norm2 {n2:.6e} vs {rec['norm2']:.6e}")
         assert err < TOL_C64
         assert abs(n2 - rec["norm2"]) < 2 * TOL_C64 * rec["norm2"]
+
+
+def test_rqc53_reconfigured_sampled_slice(torch):
+    """53-qubit workload on the reconfigured path (t = 30): one sampled
+    slice against the oracle's complex128 contraction of the same slice
+    (tests/golden/make_rqc53_reference.py --reconf 8)."""
+    import paper_2205_00393_amd as P
+    path = os.path.join(GOLDEN, "rqc53_reconf_slices.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden reconfigured rqc53 slices not generated")
+    ref = np.load(path)
+    meta = json.load(open(os.path.join(GOLDEN, "rqc53_reconf_slices.json")))
+    w = make_workload("rqc53")
+    banner("rqc53 reconfigured plan")
+    pr = P.prepare(w, reconf_k=8)
+    assert pr.sliced == meta["sliced"]
+    plan = pr.plan()
+    plan.bind(batch=1)
+    for j, rec in enumerate(meta["slices"]):
+        s = int(rec["id"])
+        banner(f"rqc53 reconfigured slice {s}")
+        out = plan.execute([s])
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        err = rel_l2(got[ref["positions"]], ref["amplitudes"][j])
+        n2 = float(np.sum(np.abs(got) ** 2))
+        banner(f"rqc53 reconfigured slice {s}: sampled rel err {err:.3e}, norm2 {n2:.6e} vs {rec['norm2']:.6e}")
+        assert err < TOL_C64
+        assert abs(n2 - rec["norm2"]) < 2 * TOL_C64 * rec["norm2"]
