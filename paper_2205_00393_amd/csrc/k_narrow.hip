@@ -34,7 +34,9 @@ __device__ __forceinline__ uint64_t pdep_n(uint64_t x, uint64_t mask) {
 
 // LDS: A tile (TM * KP elements, also the staging area of the TM * N
 // outputs) then B (N * K elements); sized per launch.
-template <int NCH>
+// Each thread computes RPT rows (TM / RPT apart) x NCH columns of a tile:
+// every A element read feeds NCH products, every B element RPT.
+template <int NCH, int RPT>
 __global__ __launch_bounds__(256) void k_narrow(NarrowDesc d) {
   extern __shared__ float2 lds[];
   float2* As = lds;
@@ -45,7 +47,8 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowDesc d) {
   const int q = d.q, K = 1 << d.k, N = 1 << d.n, TM = 1 << q;
   const int KP = K == 1 ? 1 : K + 1;
   const int NC = N / NCH;
-  const int items = TM * NC;
+  const int HR = TM / RPT;  // rows per row group
+  const int items = HR * NC;
   const int outs = TM * N;
   const int tile_elems = TM * K;
   for (int e = tid; e < 64; e += blockDim.x) {
@@ -79,39 +82,50 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowDesc d) {
       for (int e = tid; e < tile_elems; e += 256) As[e] = Ab[e];
     }
     __syncthreads();
+    constexpr int PER = 8 / (NCH * RPT);  // items per thread (<= 2048 outputs per tile)
     float2 acc[8];
 #pragma unroll
-    for (int i = 0; i < 8 / NCH; ++i) {
+    for (int i = 0; i < PER; ++i) {
       const int w = tid + 256 * i;
 #pragma unroll
-      for (int j = 0; j < NCH; ++j) acc[i * NCH + j] = make_float2(0.f, 0.f);
+      for (int j = 0; j < NCH * RPT; ++j) acc[i * NCH * RPT + j] = make_float2(0.f, 0.f);
       if (w < items) {
-        const int r = w & (TM - 1), nc = w >> q;
-        const float2* arow = As + r * KP;
+        const int r0 = w & (HR - 1), nc = w / HR;
+        const float2* arow = As + r0 * KP;
         const float2* bcol = Bs + nc * NCH * K;
         for (int kk = 0; kk < K; ++kk) {
-          const float2 a = arow[kk];
+          float2 a[RPT];
+#pragma unroll
+          for (int u = 0; u < RPT; ++u) a[u] = arow[u * HR * KP + kk];
 #pragma unroll
           for (int j = 0; j < NCH; ++j) {
             const float2 bv = bcol[j * K + kk];
-            acc[i * NCH + j].x += a.x * bv.x - a.y * bv.y;
-            acc[i * NCH + j].y += a.x * bv.y + a.y * bv.x;
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) {
+              float2& c = acc[(i * RPT + u) * NCH + j];
+              c.x += a[u].x * bv.x - a[u].y * bv.y;
+              c.y += a[u].x * bv.y + a[u].y * bv.x;
+            }
           }
         }
       }
     }
     __syncthreads();  // A tile no longer read: stage the outputs over it
 #pragma unroll
-    for (int i = 0; i < 8 / NCH; ++i) {
+    for (int i = 0; i < PER; ++i) {
       const int w = tid + 256 * i;
       if (w < items) {
-        const int r = w & (TM - 1), nc = w >> q;
-        const int tr = tR_lo[r & 63] | tR_hi[r >> 6];
+        const int r0 = w & (HR - 1), nc = w / HR;
 #pragma unroll
-        for (int j = 0; j < NCH; ++j) {
-          const float2 v = acc[i * NCH + j];
-          As[tr | tN[nc * NCH + j]] = v;
-          vmax = fmaxf(vmax, fmaxf(fabsf(v.x), fabsf(v.y)));
+        for (int u = 0; u < RPT; ++u) {
+          const int r = r0 + u * HR;
+          const int tr = tR_lo[r & 63] | tR_hi[r >> 6];
+#pragma unroll
+          for (int j = 0; j < NCH; ++j) {
+            const float2 v = acc[(i * RPT + u) * NCH + j];
+            As[tr | tN[nc * NCH + j]] = v;
+            vmax = fmaxf(vmax, fmaxf(fabsf(v.x), fabsf(v.y)));
+          }
         }
       }
     }
@@ -178,19 +192,25 @@ void launch_narrow(const NarrowDesc& d0, hipStream_t st) {
   const int TM = 1 << d.q, KP = K == 1 ? 1 : K + 1;
   d.a_elems = TM * KP > TM * N ? TM * KP : TM * N;
   const size_t lds = (size_t)(d.a_elems + N * K) * sizeof(float2);
+  // 2 rows x 4 columns per thread when the tile has >= 8 columns and >= 2
+  // rows (6 LDS reads per 8 products), else one row x up to 8 columns
+  if (N >= 8 && TM >= 2) {
+    hipLaunchKernelGGL((k_narrow<4, 2>), dim3(blocks), dim3(256), lds, st, d);
+    return;
+  }
   const int nch = N >= 8 ? 8 : N;
   switch (nch) {
     case 1:
-      hipLaunchKernelGGL(k_narrow<1>, dim3(blocks), dim3(256), lds, st, d);
+      hipLaunchKernelGGL((k_narrow<1, 1>), dim3(blocks), dim3(256), lds, st, d);
       break;
     case 2:
-      hipLaunchKernelGGL(k_narrow<2>, dim3(blocks), dim3(256), lds, st, d);
+      hipLaunchKernelGGL((k_narrow<2, 1>), dim3(blocks), dim3(256), lds, st, d);
       break;
     case 4:
-      hipLaunchKernelGGL(k_narrow<4>, dim3(blocks), dim3(256), lds, st, d);
+      hipLaunchKernelGGL((k_narrow<4, 1>), dim3(blocks), dim3(256), lds, st, d);
       break;
     default:
-      hipLaunchKernelGGL(k_narrow<8>, dim3(blocks), dim3(256), lds, st, d);
+      hipLaunchKernelGGL((k_narrow<8, 1>), dim3(blocks), dim3(256), lds, st, d);
       break;
   }
 }
