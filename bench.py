@@ -268,11 +268,11 @@ def main():
                                                     for m, r in vres.items()},
                    "modes": {m: {k: sig6(v) for k, v in r.items()} for m, r in vres.items()}}
         if args.workload == "rqc30":
-            # the same path with fused sub-paths (secondary slicing, working rank 11)
+            # the same path with fused sub-paths (secondary slicing, working rank 10)
             pr_seconds["reconf+fused"] = pr_seconds["reconf"]
-            fres, ff = run_plan(prv, ["c64"], "reconf+fused", fuse_rank=11)
+            fres, ff = run_plan(prv, ["c64"], "reconf+fused", fuse_rank=10)
             variant["fused_sub_paths"] = {
-                "fuse_rank": 11, "groups": len(ff["groups"]),
+                "fuse_rank": 10, "groups": len(ff["groups"]),
                 "steps_fused": sum(g["n_steps"] for g in ff["groups"]),
                 "c64": {k: sig6(v) for k, v in fres["c64"].items()}}
         for m, r in vres.items():

@@ -8,14 +8,16 @@
 // in LDS, and writes W_L once. HBM sees one read of T_0 and one write of T_L
 // instead of a read and a write per step.
 //
-// One block of 256 threads per piece at a time, pieces of a block taken
-// from a contiguous range (so the slice, and the small tensors staged in
-// LDS, change rarely); the next piece's input is loaded into registers
-// while the current one is computed. Stage j: W_j[pos(r, n)] = sum_k
-// W_{j-1}[r 2^k + k] Y_j[n 2^k + k] with pos(r, n) = pdep(r, cmask_j) |
-// pdep(n, ~cmask_j), linear in the bits of r and n and read from per-stage
-// tables over 6-bit halves. Each thread computes a register block
-// of up to 4 rows x 4 columns, so one LDS read feeds four multiply-adds.
+// Each wave owns one piece at a time (its own two LDS buffers), so the
+// stages need only wave-level synchronisation; the waves of a block take
+// the pieces of one round (same slice, so the small tensors staged in LDS
+// are shared) and meet at a block barrier only when the slice changes.
+// The next round's input is loaded into registers while the current piece
+// is computed. Stage j: W_j[pos(r, n)] = sum_k W_{j-1}[r 2^k + k]
+// Y_j[n 2^k + k] with pos(r, n) = pdep(r, cmask_j) | pdep(n, ~cmask_j),
+// linear in the bits of r and n and read from per-stage tables over 6-bit
+// halves; each lane computes a register block of up to 4 x 4 outputs, k in
+// a lane-rotated order against bank conflicts.
 #include "kernels.h"
 
 namespace ltn {
@@ -32,20 +34,20 @@ __device__ __forceinline__ uint64_t pdep_f(uint64_t x, uint64_t mask) {
   return r;
 }
 
-constexpr int kThreads = 256;
-constexpr int kInPer = 4096 / kThreads;  // input elements per thread (2^a <= 4096)
+constexpr int kInPer = 2048 / 64;  // input elements per lane (2^a <= 2^11)
 
-__global__ __launch_bounds__(kThreads) void k_fused(FusedDesc d) {
+template <int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_fused(FusedDesc d) {
   extern __shared__ float2 lds[];
   const int W = 1 << d.rmax;
-  float2* buf0 = lds;
-  float2* buf1 = lds + W;
-  float2* Ys = lds + 2 * W;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  float2* buf0 = lds + wave * 2 * W;
+  float2* buf1 = buf0 + W;
+  float2* Ys = lds + WPB * 2 * W;
   // rowP / nP: position in W_j of row r / column n (pdep over 6-bit halves)
   __shared__ uint16_t rowP[kFusedMaxStages][128], nP[kFusedMaxStages][128];
   __shared__ uint64_t wT[128];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < 64 * d.nstages; e += kThreads) {
+  for (int e = tid; e < 64 * d.nstages; e += 64 * WPB) {
     const int j = e >> 6, v = e & 63;
     const FusedStage& s = d.st[j];
     const uint64_t full = (1ull << (s.m + s.n)) - 1;
@@ -55,14 +57,16 @@ __global__ __launch_bounds__(kThreads) void k_fused(FusedDesc d) {
     nP[j][v] = (uint16_t)pdep_f((uint64_t)v, ncm);
     nP[j][64 + v] = (uint16_t)pdep_f((uint64_t)v << 6, ncm);
   }
-  for (int v = tid; v < 64; v += kThreads) {
+  for (int v = tid; v < 64; v += 64 * WPB) {
     wT[v] = pdep_f((uint64_t)v, d.w_out);
     wT[64 + v] = pdep_f((uint64_t)v << 6, d.w_out);
   }
-  const int64_t total = (int64_t)d.nb << d.nsig;
-  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+  // rounds of WPB consecutive pieces (2^nsig >= WPB pieces per slice, so a
+  // round never spans two slices); each block takes a contiguous range
+  const int64_t rounds = ((int64_t)d.nb << d.nsig) / WPB;
+  const int64_t per = (rounds + gridDim.x - 1) / gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * per;
-  const int64_t hi = lo + per < total ? lo + per : total;
+  const int64_t hi = lo + per < rounds ? lo + per : rounds;
   const int na = 1 << d.a, nc = 1 << d.c;
   const int64_t sig_mask = (int64_t(1) << d.nsig) - 1;
   float2 pre[kInPer];
@@ -70,49 +74,50 @@ __global__ __launch_bounds__(kThreads) void k_fused(FusedDesc d) {
     const float2* src = d.X0 + (it >> d.nsig) * d.sX0 + ((it & sig_mask) << d.a);
 #pragma unroll
     for (int i = 0; i < kInPer; ++i) {
-      const int e = tid + kThreads * i;
+      const int e = lane + 64 * i;
       if (e < na) pre[i] = src[e];
     }
   };
-  if (lo < hi) prefetch(lo);
+  if (lo < hi) prefetch(lo * WPB + wave);
   int64_t cur_b = -1;
   float vmax = 0.f;
   __syncthreads();  // tables
-  for (int64_t it = lo; it < hi; ++it) {
+  for (int64_t r = lo; r < hi; ++r) {
+    const int64_t it = r * WPB + wave;
     const int64_t b = it >> d.nsig, sig = it & sig_mask;
-    if (b != cur_b) {
+    if (b != cur_b) {  // the same for every wave of the block
       if (d.scale_c && cur_b >= 0) {
         float v = vmax;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-        if ((tid & 63) == 0) raise_max(d.scale_c + cur_b, v);
+        if (lane == 0) raise_max(d.scale_c + cur_b, v);
         vmax = 0.f;
       }
+      __syncthreads();  // every wave is done with the previous slice's tensors
       for (int j = 0; j < d.nstages; ++j) {
         const FusedStage& s = d.st[j];
         const float2* y = s.Y + b * s.sY;
         const int ny = 1 << (s.k + s.n);
-        for (int e = tid; e < ny; e += kThreads) Ys[s.yoff + e] = y[e];
+        for (int e = tid; e < ny; e += 64 * WPB) Ys[s.yoff + e] = y[e];
       }
+      __syncthreads();
       cur_b = b;
     }
 #pragma unroll
     for (int i = 0; i < kInPer; ++i) {
-      const int e = tid + kThreads * i;
+      const int e = lane + 64 * i;
       if (e < na) buf0[e] = pre[i];
     }
-    if (it + 1 < hi) prefetch(it + 1);
-    __syncthreads();
+    if (r + 1 < hi) prefetch(it + WPB);
+    __syncwarp();
     float2* in = buf0;
     float2* out = buf1;
     for (int j = 0; j < d.nstages; ++j) {
       const FusedStage& s = d.st[j];
       const int K = 1 << s.k;
       // register blocks of RB rows x NB columns, as large as 4 x 4 while
-      // every thread keeps a block (2^(m+n) / (RB NB) >= 256); k runs in a
-      // lane-dependent rotation so that lanes on rows (or columns) K apart
-      // hit distinct banks
-      int bb = s.m + s.n - 8;
+      // every lane keeps a block (2^(m+n) / (RB NB) >= 64)
+      int bb = s.m + s.n - 6;
       bb = bb < 0 ? 0 : (bb > 4 ? 4 : bb);
       int rbits = (bb + 1) / 2;
       rbits = rbits > s.m ? s.m : rbits;
@@ -122,7 +127,9 @@ __global__ __launch_bounds__(kThreads) void k_fused(FusedDesc d) {
       const int RB = 1 << rbits, NB = 1 << nbits;
       const int nrb = 1 << (s.m - rbits);
       const int blocks = nrb << (s.n - nbits);
-      for (int w = tid; w < blocks; w += kThreads) {
+      const int r1 = rowP[j][1], r2 = rowP[j][2], c1 = nP[j][1], c2 = nP[j][2];
+      const int roff[4] = {0, r1, r2, r1 | r2}, coff[4] = {0, c1, c2, c1 | c2};
+      for (int w = lane; w < blocks; w += 64) {
         const int r0 = (w & (nrb - 1)) << rbits, n0 = (w >> (s.m - rbits)) << nbits;
         float2 acc[4][4];
 #pragma unroll
@@ -132,7 +139,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(FusedDesc d) {
         const float2* ar = in + r0 * K;
         const float2* yr = Ys + s.yoff + n0 * K;
         for (int kk0 = 0; kk0 < K; ++kk0) {
-          const int kk = (kk0 + tid) & (K - 1);
+          const int kk = (kk0 + lane) & (K - 1);
           float2 x[4], y[4];
 #pragma unroll
           for (int i = 0; i < 4; ++i)
@@ -152,42 +159,53 @@ __global__ __launch_bounds__(kThreads) void k_fused(FusedDesc d) {
         // positions are linear in the bits: base of the block, then the
         // offsets of rows 1..3 and columns 1..3 (disjoint bits)
         const int base = rowP[j][r0 & 63] | rowP[j][64 + (r0 >> 6)] | nP[j][n0 & 63];
-        const int r1 = rowP[j][1], r2 = rowP[j][2], c1 = nP[j][1], c2 = nP[j][2];
-        const int roff[4] = {0, r1, r2, r1 | r2}, coff[4] = {0, c1, c2, c1 | c2};
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int q = 0; q < 4; ++q)
             if (i < RB && q < NB) out[base | roff[i] | coff[q]] = acc[i][q];
       }
-      __syncthreads();
+      __syncwarp();
       float2* tmp = in;
       in = out;
       out = tmp;
     }
     float2* dst = d.XL + b * d.sXL + pdep_f((uint64_t)sig, d.sig_out);
-    for (int w = tid; w < nc; w += kThreads) {
+    for (int w = lane; w < nc; w += 64) {
       const float2 v = in[w];
       dst[wT[w & 63] | wT[64 + (w >> 6)]] = v;
       vmax = fmaxf(vmax, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
-    __syncthreads();  // the next piece overwrites buf0 (and maybe Ys)
+    __syncwarp();  // the next piece overwrites buf0
   }
   if (d.scale_c && cur_b >= 0) {
     float v = vmax;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-    if ((tid & 63) == 0) raise_max(d.scale_c + cur_b, v);
+    if (lane == 0) raise_max(d.scale_c + cur_b, v);
   }
 }
 
 }  // namespace
 
 void launch_fused(const FusedDesc& d, hipStream_t st) {
-  const int64_t total = (int64_t)d.nb << d.nsig;
-  const int blocks = (int)(total < 1024 ? total : 1024);
-  const size_t lds = ((size_t)2 * ((size_t)1 << d.rmax) + (size_t)d.y_elems) * sizeof(float2);
-  hipLaunchKernelGGL(k_fused, dim3(blocks), dim3(kThreads), lds, st, d);
+  // waves per block: as many as keep two working buffers per wave plus the
+  // small tensors within 64 KiB of LDS
+  const int wpb = d.rmax <= 9 ? 4 : (d.rmax == 10 ? 2 : 1);
+  const int64_t rounds = ((int64_t)d.nb << d.nsig) / wpb;
+  const int blocks = (int)(rounds < 2048 ? rounds : 2048);
+  const size_t lds = ((size_t)wpb * 2 * ((size_t)1 << d.rmax) + (size_t)d.y_elems) * sizeof(float2);
+  switch (wpb) {
+    case 4:
+      hipLaunchKernelGGL(k_fused<4>, dim3(blocks), dim3(256), lds, st, d);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_fused<2>, dim3(blocks), dim3(128), lds, st, d);
+      break;
+    default:
+      hipLaunchKernelGGL(k_fused<1>, dim3(blocks), dim3(64), lds, st, d);
+      break;
+  }
 }
 
 }  // namespace ltn
