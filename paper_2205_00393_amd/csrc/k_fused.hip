@@ -36,6 +36,70 @@ __device__ __forceinline__ uint64_t pdep_f(uint64_t x, uint64_t mask) {
 
 constexpr int kInPer = 2048 / 64;  // input elements per lane (2^a <= 2^11)
 
+// One stage for a lane: register blocks of RB rows x NB columns of W_j, with
+// K = 2^kbits given at compile time when KC > 0 (the loops unroll without
+// guards); KC = 0 takes K at run time.
+template <int KC, int RB, int NB>
+__device__ __forceinline__ void stage_blocks(const float2* in, float2* out, const float2* yb, int kbits,
+                                             int m, int n, int rbits, int nbits,
+                                             const uint16_t* rowPj, const uint16_t* nPj, int lane) {
+  const int K = KC > 0 ? KC : (1 << kbits);
+  const int nrb = 1 << (m - rbits);
+  const int blocks = nrb << (n - nbits);
+  const int r1 = rowPj[1], r2 = rowPj[2], c1 = nPj[1], c2 = nPj[2];
+  const int roff[4] = {0, r1, r2, r1 | r2}, coff[4] = {0, c1, c2, c1 | c2};
+  for (int w = lane; w < blocks; w += 64) {
+    const int r0 = (w & (nrb - 1)) << rbits, n0 = (w >> (m - rbits)) << nbits;
+    float2 acc[RB][NB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int q = 0; q < NB; ++q) acc[i][q] = make_float2(0.f, 0.f);
+    const float2* ar = in + r0 * K;
+    const float2* yr = yb + n0 * K;
+    auto step = [&](int kk0) {
+      const int kk = (kk0 + lane) & (K - 1);
+      float2 x[RB], y[NB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) x[i] = ar[i * K + kk];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) y[q] = yr[q * K + kk];
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          acc[i][q].x += x[i].x * y[q].x - x[i].y * y[q].y;
+          acc[i][q].y += x[i].x * y[q].y + x[i].y * y[q].x;
+        }
+    };
+    if constexpr (KC > 0) {
+#pragma unroll
+      for (int kk0 = 0; kk0 < KC; ++kk0) step(kk0);
+    } else {
+      for (int kk0 = 0; kk0 < K; ++kk0) step(kk0);
+    }
+    // positions are linear in the bits: base of the block, then the offsets
+    // of rows 1..3 and columns 1..3 (disjoint bits)
+    const int base = rowPj[r0 & 63] | rowPj[64 + (r0 >> 6)] | nPj[n0 & 63];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int q = 0; q < NB; ++q) out[base | roff[i] | coff[q]] = acc[i][q];
+  }
+}
+
+template <int RB, int NB>
+__device__ __forceinline__ void stage_k(const float2* in, float2* out, const float2* yb, int kbits,
+                                        int m, int n, int rbits, int nbits, const uint16_t* rowPj,
+                                        const uint16_t* nPj, int lane) {
+  switch (kbits) {
+    case 1: stage_blocks<2, RB, NB>(in, out, yb, kbits, m, n, rbits, nbits, rowPj, nPj, lane); break;
+    case 2: stage_blocks<4, RB, NB>(in, out, yb, kbits, m, n, rbits, nbits, rowPj, nPj, lane); break;
+    case 3: stage_blocks<8, RB, NB>(in, out, yb, kbits, m, n, rbits, nbits, rowPj, nPj, lane); break;
+    default: stage_blocks<0, RB, NB>(in, out, yb, kbits, m, n, rbits, nbits, rowPj, nPj, lane); break;
+  }
+}
+
 template <int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_fused(FusedDesc d) {
   extern __shared__ float2 lds[];
@@ -124,46 +188,18 @@ __global__ __launch_bounds__(64 * WPB) void k_fused(FusedDesc d) {
       int nbits = bb - rbits;
       nbits = nbits > s.n ? s.n : nbits;
       rbits = bb - nbits > s.m ? s.m : bb - nbits;
-      const int RB = 1 << rbits, NB = 1 << nbits;
-      const int nrb = 1 << (s.m - rbits);
-      const int blocks = nrb << (s.n - nbits);
-      const int r1 = rowP[j][1], r2 = rowP[j][2], c1 = nP[j][1], c2 = nP[j][2];
-      const int roff[4] = {0, r1, r2, r1 | r2}, coff[4] = {0, c1, c2, c1 | c2};
-      for (int w = lane; w < blocks; w += 64) {
-        const int r0 = (w & (nrb - 1)) << rbits, n0 = (w >> (s.m - rbits)) << nbits;
-        float2 acc[4][4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) acc[i][q] = make_float2(0.f, 0.f);
-        const float2* ar = in + r0 * K;
-        const float2* yr = Ys + s.yoff + n0 * K;
-        for (int kk0 = 0; kk0 < K; ++kk0) {
-          const int kk = (kk0 + lane) & (K - 1);
-          float2 x[4], y[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (i < RB) x[i] = ar[i * K + kk];
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (q < NB) y[q] = yr[q * K + kk];
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              if (i < RB && q < NB) {
-                acc[i][q].x += x[i].x * y[q].x - x[i].y * y[q].y;
-                acc[i][q].y += x[i].x * y[q].y + x[i].y * y[q].x;
-              }
-        }
-        // positions are linear in the bits: base of the block, then the
-        // offsets of rows 1..3 and columns 1..3 (disjoint bits)
-        const int base = rowP[j][r0 & 63] | rowP[j][64 + (r0 >> 6)] | nP[j][n0 & 63];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (i < RB && q < NB) out[base | roff[i] | coff[q]] = acc[i][q];
+      const int code = (rbits << 2) | nbits;
+      const float2* yb = Ys + s.yoff;
+      switch (code) {
+        case (2 << 2) | 2: stage_k<4, 4>(in, out, yb, s.k, s.m, s.n, rbits, nbits, rowP[j], nP[j], lane); break;
+        case (2 << 2) | 1: stage_k<4, 2>(in, out, yb, s.k, s.m, s.n, rbits, nbits, rowP[j], nP[j], lane); break;
+        case (1 << 2) | 2: stage_k<2, 4>(in, out, yb, s.k, s.m, s.n, rbits, nbits, rowP[j], nP[j], lane); break;
+        case (1 << 2) | 1: stage_k<2, 2>(in, out, yb, s.k, s.m, s.n, rbits, nbits, rowP[j], nP[j], lane); break;
+        case (2 << 2) | 0: stage_k<4, 1>(in, out, yb, s.k, s.m, s.n, rbits, nbits, rowP[j], nP[j], lane); break;
+        case (0 << 2) | 2: stage_k<1, 4>(in, out, yb, s.k, s.m, s.n, rbits, nbits, rowP[j], nP[j], lane); break;
+        case (1 << 2) | 0: stage_k<2, 1>(in, out, yb, s.k, s.m, s.n, rbits, nbits, rowP[j], nP[j], lane); break;
+        case (0 << 2) | 1: stage_k<1, 2>(in, out, yb, s.k, s.m, s.n, rbits, nbits, rowP[j], nP[j], lane); break;
+        default: stage_k<1, 1>(in, out, yb, s.k, s.m, s.n, rbits, nbits, rowP[j], nP[j], lane); break;
       }
       __syncwarp();
       float2* tmp = in;
