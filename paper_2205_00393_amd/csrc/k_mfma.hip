@@ -83,6 +83,45 @@ __device__ __forceinline__ void tile_of(int64_t w, int64_t tiles_m, int64_t tile
   bn = r / G;
 }
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool BF>
+struct SplitType;
+template <>
+struct SplitType<false> {
+  using T = _Float16;
+  typedef _Float16 V8 __attribute__((ext_vector_type(8)));
+  static constexpr int S = 11;
+};
+template <>
+struct SplitType<true> {
+  using T = __bf16;
+  typedef __bf16 V8 __attribute__((ext_vector_type(8)));
+  static constexpr int S = 0;
+};
+
+template <bool BF>
+__device__ __forceinline__ uint32_t split_pair(float a, float b, float sigma, uint32_t& lo) {
+  using T = typename SplitType<BF>::T;
+  constexpr float P = (float)(1 << SplitType<BF>::S);
+  float xa = a * sigma, xb = b * sigma;
+  T ha = (T)xa, hb = (T)xb;
+  T la = (T)((xa - (float)ha) * P), lb = (T)((xb - (float)hb) * P);
+  lo = (uint32_t)__builtin_bit_cast(uint16_t, la) | ((uint32_t)__builtin_bit_cast(uint16_t, lb) << 16);
+  return (uint32_t)__builtin_bit_cast(uint16_t, ha) | ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
+}
+
+// One complex output written in the bf16 split layout (groups of 4
+// consecutive complex: 16 bytes of hi words, then 16 bytes of lo words; a
+// word holds (re, im)); the same bits as the conversion pass produces.
+__device__ __forceinline__ void store_split_bf16(uint32_t* Cw, uint64_t addr, float re, float im) {
+  uint32_t lo;
+  const uint32_t hi = split_pair<true>(re, im, 1.f, lo);
+  uint32_t* g = Cw + (addr >> 2) * 8 + (addr & 3);
+  g[0] = hi;
+  g[4] = lo;
+}
+
 template <int BM, int BNC, int BKC>
 struct Cfg {
   static constexpr int WM = BM / 2;          // rows per wave
@@ -110,6 +149,7 @@ __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
   const float2* A = d.A + b * d.sA + bm * BM * K;
   const float2* B = d.B + b * d.sB + bn * BNC * K;
   float* Cf = reinterpret_cast<float*>(d.C + b * d.sC);
+  uint32_t* Cw = reinterpret_cast<uint32_t*>(d.C + b * d.sC);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -221,29 +261,22 @@ __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
           uint64_t addr = pbase | pt[x] | pg[g] | pq[q] | pn;
           float v = acc[x][y][4 * g + q];
           vmax = fmaxf(vmax, fabsf(v));
-          Cf[2 * addr + (im_col ? 1 : 0)] = v;
+          if (d.split_out) {
+            // re and im of this output sit on neighbouring lanes: the even
+            // lane writes the hi word, the odd lane the lo word
+            const float o = __shfl_xor(v, 1, 64);
+            const float re = im_col ? o : v, im = im_col ? v : o;
+            uint32_t lo;
+            const uint32_t hi = split_pair<true>(re, im, 1.f, lo);
+            Cw[(addr >> 2) * 8 + (im_col ? 4 : 0) + (addr & 3)] = im_col ? lo : hi;
+          } else {
+            Cf[2 * addr + (im_col ? 1 : 0)] = v;
+          }
         }
   }
   if (d.scale_c) record_max(d.scale_c + b, vmax);
 }
 
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-template <bool BF>
-struct SplitType;
-template <>
-struct SplitType<false> {
-  using T = _Float16;
-  typedef _Float16 V8 __attribute__((ext_vector_type(8)));
-  static constexpr int S = 11;
-};
-template <>
-struct SplitType<true> {
-  using T = __bf16;
-  typedef __bf16 V8 __attribute__((ext_vector_type(8)));
-  static constexpr int S = 0;
-};
 
 template <bool BF>
 __device__ __forceinline__ floatx16 mfma16(u32x4 a, u32x4 b, floatx16 c) {
@@ -271,17 +304,6 @@ __device__ __forceinline__ u32x4 times2048(u32x4 w) {
   H8 h = __builtin_bit_cast(H8, w);
   h = h * (_Float16)2048.0f;
   return __builtin_bit_cast(u32x4, h);
-}
-
-template <bool BF>
-__device__ __forceinline__ uint32_t split_pair(float a, float b, float sigma, uint32_t& lo) {
-  using T = typename SplitType<BF>::T;
-  constexpr float P = (float)(1 << SplitType<BF>::S);
-  float xa = a * sigma, xb = b * sigma;
-  T ha = (T)xa, hb = (T)xb;
-  T la = (T)((xa - (float)ha) * P), lb = (T)((xb - (float)hb) * P);
-  lo = (uint32_t)__builtin_bit_cast(uint16_t, la) | ((uint32_t)__builtin_bit_cast(uint16_t, lb) << 16);
-  return (uint32_t)__builtin_bit_cast(uint16_t, ha) | ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
 }
 
 // complex64 -> split layout of one tensor for nb slices (src and dst may
@@ -487,7 +509,10 @@ __global__ __launch_bounds__(256, (BM * BNC >= 16384 && BKC >= 32) ? 1 : (BM * B
           uint64_t addr = pbase | pt[x] | pg[g] | pq[q] | pn;
           float vr = are[x][y][4 * g + q] * post, vi = aim[x][y][4 * g + q] * post;
           vmax = fmaxf(vmax, fmaxf(fabsf(vr), fabsf(vi)));
-          Cc[addr] = make_float2(vr, vi);
+          if (BF && d.split_out)
+            store_split_bf16(reinterpret_cast<uint32_t*>(Cc), addr, vr, vi);
+          else
+            Cc[addr] = make_float2(vr, vi);
         }
   }
   if (d.scale_c) record_max(d.scale_c + b, vmax);

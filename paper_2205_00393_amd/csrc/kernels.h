@@ -91,6 +91,7 @@ struct GemmDesc {
   const uint32_t* scale_a;   // split modes: per-slice max |x| (float bits) of A
   const uint32_t* scale_b;   //              and of B
   uint32_t* scale_c;         // if set: record the output's per-slice max |x|
+  int32_t split_out;         // 1: write C in the bf16 split layout (split_bf16 only)
 };
 // Tile plan of a bit permutation (built on the host by ltn_permute).
 struct PermuteDesc {

@@ -132,6 +132,22 @@ uint32_t* slot(ltn_plan* p, int tensor) {
   return reinterpret_cast<uint32_t*>(r.ws + r.lay.scales) + (size_t)tensor * r.B;
 }
 
+// split_bf16: a tensor that a matrix-core step produces and a split step
+// consumes is written by its producer in the split layout (bf16 needs no
+// scale, so the producer's epilogue can split), and the conversion pass
+// before the consumer is skipped. Steps run inside a fused sub-path read and
+// write complex64, and the gradient's recomputed forward stays complex64.
+bool split_direct(ltn_plan* p, int t, int mode, bool gradarena) {
+  if (mode != LTN_SPLIT_BF16 || gradarena) return false;
+  auto& r = *p->rt;
+  const TensorPlan& T = p->tensors[t];
+  if (T.producer < 0 || T.consumer < 0) return false;
+  auto fused = [&](int s) { return r.fuse && p->step_group[s] >= 0; };
+  if (fused(T.producer) || fused(T.consumer)) return false;
+  const int kp = r.choice[mode][T.producer].kind, kc = r.choice[mode][T.consumer].kind;
+  return (kp == 1 || kp == 2) && kc == 2;
+}
+
 void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena, int mode) {
   auto& r = *p->rt;
   const StepPlan& sp = p->steps[s];
@@ -177,12 +193,20 @@ void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena, int mode) {
     d.cfg = ch.cfg;
     const bool f16 = mode == LTN_SPLIT_F16;
     if (f16) d.scale_c = slot(p, sp.out);
+    d.split_out = split_direct(p, sp.out, mode, gradarena) ? 1 : 0;
     if (ch.kind == 2) {
-      // split-layout copies of both operands in the per-batch scratch area
+      // split-layout copies of both operands in the per-batch scratch area,
+      // unless the producer wrote them so
       float2* As = reinterpret_cast<float2*>(r.ws + r.lay.split);
       float2* Bs = As + (((ta.bytes() + 255) / 256 * 256) / 8) * (uint64_t)r.B;
-      launch_split_convert(A, As, ta.rank, nb, f16 ? slot(p, sp.a) : nullptr, mode, r.st);
-      launch_split_convert(B, Bs, tb.rank, nb, f16 ? slot(p, sp.b) : nullptr, mode, r.st);
+      if (split_direct(p, sp.a, mode, gradarena))
+        As = A;
+      else
+        launch_split_convert(A, As, ta.rank, nb, f16 ? slot(p, sp.a) : nullptr, mode, r.st);
+      if (split_direct(p, sp.b, mode, gradarena))
+        Bs = B;
+      else
+        launch_split_convert(B, Bs, tb.rank, nb, f16 ? slot(p, sp.b) : nullptr, mode, r.st);
       d.A = sw ? Bs : As;
       d.B = sw ? As : Bs;
       if (f16) {

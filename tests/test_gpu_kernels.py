@@ -90,3 +90,60 @@ def test_set_step_kernel_rejects_misfits(torch, prepared):
     for k in big[:1]:
         with pytest.raises(P.LtnError, match="narrow"):
             plan.set_step_kernel(k, "c64", 3, 0, 0, 1)
+
+
+def _force_kind(P, plan, k, mode, kind):
+    for cfg in range(16):
+        for swap in (0, 1):
+            try:
+                plan.set_step_kernel(k, mode, kind, cfg, swap, 1)
+                return True
+            except P.LtnError:
+                continue
+    return False
+
+
+def test_split_bf16_producer_writes_split_layout(torch, prepared_fat):
+    """split_bf16: a tensor that a matrix-core step produces (complex64 or
+    split tile) and a split step consumes is written by the producer in the
+    split layout and read without a conversion pass. Every step that takes
+    a split tile gets one, other matrix-core steps a complex64 tile; then the
+    producer of the first split step fed by a split step is switched to a
+    complex64 tile, so that both producer kinds feed split consumers. The
+    result must match the state vector."""
+    import paper_2205_00393_amd as P
+    w, pr, ref = prepared_fat
+    plan = pr.plan()
+    n = 1 << len(pr.sliced)
+    plan.bind(batch=min(n, 4), budget_bytes=1 << 30)
+    steps = plan.steps()
+    kind_of = {}
+    for k in range(len(steps)):
+        for kind in (2, 1):
+            if _force_kind(P, plan, k, "split_bf16", kind):
+                kind_of[k] = kind
+                break
+    producer = {st["out"]: k for k, st in enumerate(steps)}
+
+    def feeds():
+        pairs = []
+        for k, st in enumerate(steps):
+            if kind_of.get(k) == 2:
+                for t in (st["left"], st["right"]):
+                    pk = producer.get(t)
+                    if pk is not None and kind_of.get(pk) in (1, 2):
+                        pairs.append((pk, k))
+        return pairs
+
+    first = next((pk for pk, k in feeds() if kind_of[pk] == 2), None)
+    assert first is not None, "no split step is fed by a split step"
+    assert _force_kind(P, plan, first, "split_bf16", 1)
+    kind_of[first] = 1
+    kinds = {kind_of[pk] for pk, _ in feeds()}
+    banner(f"split_bf16 direct operands: {len(feeds())} producer->split pairs, producer kinds {sorted(kinds)}")
+    assert kinds == {1, 2}
+    out = plan.execute_range(0, n, mode="split_bf16")
+    torch.cuda.synchronize()
+    err = rel_l2(out.cpu().numpy(), ref)
+    banner(f"split_bf16 with direct split operands: rel err {err:.3e}")
+    assert err < 5e-4
