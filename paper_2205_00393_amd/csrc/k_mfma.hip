@@ -111,15 +111,26 @@ __device__ __forceinline__ uint32_t split_pair(float a, float b, float sigma, ui
   return (uint32_t)__builtin_bit_cast(uint16_t, ha) | ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
 }
 
-// One complex output written in the bf16 split layout (groups of 4
-// consecutive complex: 16 bytes of hi words, then 16 bytes of lo words; a
-// word holds (re, im)); the same bits as the conversion pass produces.
-__device__ __forceinline__ void store_split_bf16(uint32_t* Cw, uint64_t addr, float re, float im) {
+// One complex output written in the split layout (groups of 4 consecutive
+// complex: 16 bytes of hi words, then 16 bytes of lo words; a word holds
+// (re, im)); the same bits as the conversion pass produces with scale sigma.
+template <bool BF>
+__device__ __forceinline__ void store_split(uint32_t* Cw, uint64_t addr, float re, float im, float sigma) {
   uint32_t lo;
-  const uint32_t hi = split_pair<true>(re, im, 1.f, lo);
+  const uint32_t hi = split_pair<BF>(re, im, sigma, lo);
   uint32_t* g = Cw + (addr >> 2) * 8 + (addr & 3);
   g[0] = hi;
   g[4] = lo;
+}
+
+// Scale of an fp16 split output written by its producer: from the bound
+// |Re c|, |Im c| <= |c| <= K max|a| max|b| <= 2 K max|Re, Im a| max|Re, Im b|
+// (the output's own maximum is not known before it is written). One thread
+// stores the bound for the consumer, which derives the same scale from it.
+__device__ __forceinline__ float split_out_scale(const GemmDesc& d, int64_t b, int64_t K, bool store) {
+  const float bound = 2.f * (float)K * __uint_as_float(d.max_a[b]) * __uint_as_float(d.max_b[b]);
+  if (store) d.bound_c[b] = __float_as_uint(bound);
+  return scale_of(__float_as_uint(bound));
 }
 
 template <int BM, int BNC, int BKC>
@@ -149,6 +160,7 @@ __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
   const float2* A = d.A + b * d.sA + bm * BM * K;
   const float2* B = d.B + b * d.sB + bn * BNC * K;
   float* Cf = reinterpret_cast<float*>(d.C + b * d.sC);
+  const float so = d.split_out == 2 ? split_out_scale(d, b, K, bm == 0 && bn == 0 && threadIdx.x == 0) : 1.f;
   uint32_t* Cw = reinterpret_cast<uint32_t*>(d.C + b * d.sC);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -266,8 +278,11 @@ __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
             // lane writes the hi word, the odd lane the lo word
             const float o = __shfl_xor(v, 1, 64);
             const float re = im_col ? o : v, im = im_col ? v : o;
-            uint32_t lo;
-            const uint32_t hi = split_pair<true>(re, im, 1.f, lo);
+            uint32_t lo, hi;
+            if (d.split_out == 1)
+              hi = split_pair<true>(re, im, 1.f, lo);
+            else
+              hi = split_pair<false>(re, im, so, lo);
             Cw[(addr >> 2) * 8 + (im_col ? 4 : 0) + (addr & 3)] = im_col ? lo : hi;
           } else {
             Cf[2 * addr + (im_col ? 1 : 0)] = v;
@@ -366,6 +381,7 @@ __global__ __launch_bounds__(256, (BM * BNC >= 16384 && BKC >= 32) ? 1 : (BM * B
   tile_of(blockIdx.x, M / BM, N / BNC, d.nb, b, bm, bn);
 
   const float sa = BF ? 1.f : scale_of(d.scale_a[b]), sb = BF ? 1.f : scale_of(d.scale_b[b]);
+  const float so = !BF && d.split_out ? split_out_scale(d, b, K, bm == 0 && bn == 0 && threadIdx.x == 0) : 1.f;
   // operands in split layout: a row of K complex is K / 4 groups of 32 bytes
   const u32x4* A = reinterpret_cast<const u32x4*>(d.A + b * d.sA + bm * BM * K);
   const u32x4* B = reinterpret_cast<const u32x4*>(d.B + b * d.sB + bn * BNC * K);
@@ -509,8 +525,8 @@ __global__ __launch_bounds__(256, (BM * BNC >= 16384 && BKC >= 32) ? 1 : (BM * B
           uint64_t addr = pbase | pt[x] | pg[g] | pq[q] | pn;
           float vr = are[x][y][4 * g + q] * post, vi = aim[x][y][4 * g + q] * post;
           vmax = fmaxf(vmax, fmaxf(fabsf(vr), fabsf(vi)));
-          if (BF && d.split_out)
-            store_split_bf16(reinterpret_cast<uint32_t*>(Cc), addr, vr, vi);
+          if (d.split_out)
+            store_split<BF>(reinterpret_cast<uint32_t*>(Cc), addr, vr, vi, so);
           else
             Cc[addr] = make_float2(vr, vi);
         }

@@ -91,7 +91,10 @@ struct GemmDesc {
   const uint32_t* scale_a;   // split modes: per-slice max |x| (float bits) of A
   const uint32_t* scale_b;   //              and of B
   uint32_t* scale_c;         // if set: record the output's per-slice max |x|
-  int32_t split_out;         // 1: write C in the bf16 split layout (split_bf16 only)
+  int32_t split_out;         // write C in the split layout: 0 no, 1 bf16, 2 fp16
+  const uint32_t* max_a;     // split_out 2: recorded max |Re|, |Im| of A and of B,
+  const uint32_t* max_b;     //   whose bound 2 K max_a max_b sets C's fp16 scale
+  uint32_t* bound_c;         //   and is stored here per slice for the consumer
 };
 // Tile plan of a bit permutation (built on the host by ltn_permute).
 struct PermuteDesc {

@@ -82,8 +82,8 @@ Layout layout(const ltn_plan* p, int B, int grad) {
   o = al(o + (size_t)npl * 8 * sizeof(double));
   l.ids = o;
   o = al(o + (size_t)B * 8);
-  l.scales = o;
-  o = al(o + (size_t)B * p->tensors.size() * 4);
+  l.scales = o;  // per tensor and slice: max |Re|, |Im|; then split_f16 bounds
+  o = al(o + (size_t)B * p->tensors.size() * 8);
   l.arena = o;
   o = al(o + (size_t)B * (grad ? p->garena : p->arena));
   l.split = o;
@@ -132,13 +132,21 @@ uint32_t* slot(ltn_plan* p, int tensor) {
   return reinterpret_cast<uint32_t*>(r.ws + r.lay.scales) + (size_t)tensor * r.B;
 }
 
-// split_bf16: a tensor that a matrix-core step produces and a split step
-// consumes is written by its producer in the split layout (bf16 needs no
-// scale, so the producer's epilogue can split), and the conversion pass
-// before the consumer is skipped. Steps run inside a fused sub-path read and
-// write complex64, and the gradient's recomputed forward stays complex64.
+// split_f16: the bound whose scale a producer used to write the tensor in
+// the split layout (read by the consumer in place of the tensor's maximum)
+uint32_t* bound_slot(ltn_plan* p, int tensor) {
+  return slot(p, (int)p->tensors.size() + tensor);
+}
+
+// Split modes: a tensor that a matrix-core step produces and a split step
+// consumes is written by its producer in the split layout, and the
+// conversion pass before the consumer is skipped. bf16 needs no scale; for
+// fp16 the producer cannot know its output's maximum before writing, so it
+// scales by the bound 2 K max|a| max|b| taken from its operands' recorded
+// maxima (stored for the consumer). Steps run inside a fused sub-path read
+// and write complex64, and the gradient's recomputed forward stays complex64.
 bool split_direct(ltn_plan* p, int t, int mode, bool gradarena) {
-  if (mode != LTN_SPLIT_BF16 || gradarena) return false;
+  if (mode == LTN_C64 || gradarena) return false;
   auto& r = *p->rt;
   const TensorPlan& T = p->tensors[t];
   if (T.producer < 0 || T.consumer < 0) return false;
@@ -193,7 +201,14 @@ void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena, int mode) {
     d.cfg = ch.cfg;
     const bool f16 = mode == LTN_SPLIT_F16;
     if (f16) d.scale_c = slot(p, sp.out);
-    d.split_out = split_direct(p, sp.out, mode, gradarena) ? 1 : 0;
+    if (split_direct(p, sp.out, mode, gradarena)) {
+      d.split_out = f16 ? 2 : 1;
+      if (f16) {
+        d.max_a = slot(p, sw ? sp.b : sp.a);
+        d.max_b = slot(p, sw ? sp.a : sp.b);
+        d.bound_c = bound_slot(p, sp.out);
+      }
+    }
     if (ch.kind == 2) {
       // split-layout copies of both operands in the per-batch scratch area,
       // unless the producer wrote them so
@@ -210,8 +225,11 @@ void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena, int mode) {
       d.A = sw ? Bs : As;
       d.B = sw ? As : Bs;
       if (f16) {
-        d.scale_a = slot(p, sw ? sp.b : sp.a);
-        d.scale_b = slot(p, sw ? sp.a : sp.b);
+        // the maximum the operand's split copy was scaled by, or the bound
+        // its producer used
+        const int ra = sw ? sp.b : sp.a, rb = sw ? sp.a : sp.b;
+        d.scale_a = split_direct(p, ra, mode, gradarena) ? bound_slot(p, ra) : slot(p, ra);
+        d.scale_b = split_direct(p, rb, mode, gradarena) ? bound_slot(p, rb) : slot(p, rb);
       }
     }
     launch_cgemm(d, ch.kind == 2 ? mode : LTN_C64, r.st);

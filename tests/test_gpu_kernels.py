@@ -103,10 +103,12 @@ def _force_kind(P, plan, k, mode, kind):
     return False
 
 
-def test_split_bf16_producer_writes_split_layout(torch, prepared_fat):
-    """split_bf16: a tensor that a matrix-core step produces (complex64 or
+@pytest.mark.parametrize("mode", ["split_f16", "split_bf16"])
+def test_split_producer_writes_split_layout(torch, prepared_fat, mode):
+    """Split modes: a tensor that a matrix-core step produces (complex64 or
     split tile) and a split step consumes is written by the producer in the
-    split layout and read without a conversion pass. Every step that takes
+    split layout (fp16: scaled by the bound 2 K max|a| max|b| from its
+    operands' maxima) and read without a conversion pass. Every step that takes
     a split tile gets one, other matrix-core steps a complex64 tile; then the
     producer of the first split step fed by a split step is switched to a
     complex64 tile, so that both producer kinds feed split consumers. The
@@ -120,7 +122,7 @@ def test_split_bf16_producer_writes_split_layout(torch, prepared_fat):
     kind_of = {}
     for k in range(len(steps)):
         for kind in (2, 1):
-            if _force_kind(P, plan, k, "split_bf16", kind):
+            if _force_kind(P, plan, k, mode, kind):
                 kind_of[k] = kind
                 break
     producer = {st["out"]: k for k, st in enumerate(steps)}
@@ -137,13 +139,13 @@ def test_split_bf16_producer_writes_split_layout(torch, prepared_fat):
 
     first = next((pk for pk, k in feeds() if kind_of[pk] == 2), None)
     assert first is not None, "no split step is fed by a split step"
-    assert _force_kind(P, plan, first, "split_bf16", 1)
+    assert _force_kind(P, plan, first, mode, 1)
     kind_of[first] = 1
     kinds = {kind_of[pk] for pk, _ in feeds()}
-    banner(f"split_bf16 direct operands: {len(feeds())} producer->split pairs, producer kinds {sorted(kinds)}")
+    banner(f"{mode} direct operands: {len(feeds())} producer->split pairs, producer kinds {sorted(kinds)}")
     assert kinds == {1, 2}
-    out = plan.execute_range(0, n, mode="split_bf16")
+    out = plan.execute_range(0, n, mode=mode)
     torch.cuda.synchronize()
     err = rel_l2(out.cpu().numpy(), ref)
-    banner(f"split_bf16 with direct split operands: rel err {err:.3e}")
+    banner(f"{mode} with direct split operands: rel err {err:.3e}")
     assert err < 5e-4
