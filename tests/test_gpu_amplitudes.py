@@ -253,9 +253,10 @@ def test_rqc30_split_full_size(torch, mode):
 
 def test_rqc53_sampled_slice(torch):
     """53-qubit workload at full size (t = 30, |S| = 68): one sampled slice
-    (2^20 amplitudes) against the oracle's complex128 contraction of the
-    same slice, stored by tests/golden/make_rqc53_reference.py (4096 seeded
-    amplitudes and the block's squared norm)."""
+    (2^20 amplitudes) in complex64, split fp16 and split bf16 against the
+    oracle's complex128 contraction of the same slice, stored by
+    tests/golden/make_rqc53_reference.py (4096 seeded amplitudes and the
+    block's squared norm)."""
     import paper_2205_00393_amd as P
     path = os.path.join(GOLDEN, "rqc53_slices.npz")
     if not os.path.exists(path):
@@ -270,20 +271,22 @@ def test_rqc53_sampled_slice(torch):
     plan.bind(batch=1)
     for j, rec in enumerate(meta["slices"]):
         s = int(rec["id"])
-        banner(f"rqc53 slice {s}")
-        out = plan.execute([s])
-        torch.cuda.synchronize()
-        got = out.cpu().numpy()
-        err = rel_l2(got[ref["positions"]], ref["amplitudes"][j])
-        n2 = float(np.sum(np.abs(got) ** 2))
-        banner(f"rqc53 slice {s}: sampled rel err {err:.3e}, norm2 {n2:.6e} vs {rec['norm2']:.6e}")
-        assert err < TOL_C64
-        assert abs(n2 - rec["norm2"]) < 2 * TOL_C64 * rec["norm2"]
+        for mode, tol in (("c64", TOL_C64), ("split_f16", TOL_SPLIT), ("split_bf16", TOL_SPLIT)):
+            banner(f"rqc53 slice {s} {mode}")
+            out = plan.execute([s], mode=mode)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            err = rel_l2(got[ref["positions"]], ref["amplitudes"][j])
+            n2 = float(np.sum(np.abs(got) ** 2))
+            banner(f"rqc53 slice {s} {mode}: sampled rel err {err:.3e}, norm2 {n2:.6e} vs {rec['norm2']:.6e}")
+            assert err < tol
+            assert abs(n2 - rec["norm2"]) < 2 * tol * rec["norm2"]
 
 
 def test_rqc53_reconfigured_sampled_slice(torch):
     """53-qubit workload on the reconfigured path (t = 30): one sampled
-    slice against the oracle's complex128 contraction of the same slice
+    slice in all three modes against the oracle's complex128 contraction of
+    the same slice
     (tests/golden/make_rqc53_reference.py --reconf 8)."""
     import paper_2205_00393_amd as P
     path = os.path.join(GOLDEN, "rqc53_reconf_slices.npz")
@@ -299,12 +302,13 @@ def test_rqc53_reconfigured_sampled_slice(torch):
     plan.bind(batch=1)
     for j, rec in enumerate(meta["slices"]):
         s = int(rec["id"])
-        banner(f"rqc53 reconfigured slice {s}")
-        out = plan.execute([s])
-        torch.cuda.synchronize()
-        got = out.cpu().numpy()
-        err = rel_l2(got[ref["positions"]], ref["amplitudes"][j])
-        n2 = float(np.sum(np.abs(got) ** 2))
-        banner(f"rqc53 reconfigured slice {s}: sampled rel err {err:.3e}, norm2 {n2:.6e} vs {rec['norm2']:.6e}")
-        assert err < TOL_C64
-        assert abs(n2 - rec["norm2"]) < 2 * TOL_C64 * rec["norm2"]
+        for mode, tol in (("c64", TOL_C64), ("split_f16", TOL_SPLIT), ("split_bf16", TOL_SPLIT)):
+            banner(f"rqc53 reconfigured slice {s} {mode}")
+            out = plan.execute([s], mode=mode)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            err = rel_l2(got[ref["positions"]], ref["amplitudes"][j])
+            n2 = float(np.sum(np.abs(got) ** 2))
+            banner(f"rqc53 reconfigured slice {s} {mode}: sampled rel err {err:.3e}, norm2 {n2:.6e} vs {rec['norm2']:.6e}")
+            assert err < tol
+            assert abs(n2 - rec["norm2"]) < 2 * tol * rec["norm2"]
