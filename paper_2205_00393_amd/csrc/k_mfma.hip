@@ -359,7 +359,18 @@ struct SplitCfg {
 // Two or three waves per SIMD where the registers allow it without spilling (the
 // accumulators then live in VGPRs), so that one block's LDS staging and
 // barriers overlap another block's matrix work.
-template <int BM, int BNC, int BKC, bool BF>
+//
+// Two ways of staging the operand tiles in LDS (DMA template flag):
+//  * through registers: each k-tile is loaded into registers while the
+//    previous one is computed, then written to LDS between two barriers;
+//    LDS rows are padded (row r starts at unit U r + r / (16 / U));
+//  * DMA: global_load_lds writes each wave's 64 x 16 bytes straight into
+//    LDS (lane i to unit i of the destination), two LDS stages, one barrier
+//    per k-tile, no staging registers. Each lane picks its global chunk so
+//    that unit U r + (g ^ sw(r)) of a part array holds group g of row r,
+//    sw(r) = (r / (16 / U)) mod U: 16 consecutive rows at one group then fall
+//    on 16 distinct units (all 64 banks) as with the padding.
+template <int BM, int BNC, int BKC, bool BF, bool DMA>
 __global__ __launch_bounds__(256, (BM * BNC >= 16384 && BKC >= 32) ? 1 : (BM * BNC >= 16384 || BKC >= 32 ? 2 : 3)) void k_cgemm_split(GemmDesc d) {
   using C = SplitCfg<BM, BNC, BKC>;
   // LDS rows of U 16-byte units (one unit = 4 complex of hi or lo parts);
@@ -372,9 +383,20 @@ __global__ __launch_bounds__(256, (BM * BNC >= 16384 && BKC >= 32) ? 1 : (BM * B
   constexpr int CHB = BNC * U * 2;
   constexpr int RA = (CHA + 255) / 256, RB = (CHB + 255) / 256;
   static_assert(BM % RPP == 0 && BNC % RPP == 0, "tile rows must fill store passes");
-  __shared__ u32x4 Ahi[BM * U + BM / RPP], Alo[BM * U + BM / RPP];
-  __shared__ u32x4 Bhi[BNC * U + BNC / RPP], Blo[BNC * U + BNC / RPP];
-  auto unit = [](int row, int g) { return U * row + row / RPP + g; };
+  constexpr int SA = BM * U, SB = BNC * U;  // DMA: units per part array and stage
+  static_assert(!DMA || (SA % 64 == 0 && SB % 64 == 0 && ((SA + SB) / 32) % 4 == 0),
+                "DMA staging needs whole 64-unit slots, a multiple of 4 per stage");
+  __shared__ u32x4 Ahi[DMA ? 1 : BM * U + BM / RPP], Alo[DMA ? 1 : BM * U + BM / RPP];
+  __shared__ u32x4 Bhi[DMA ? 1 : BNC * U + BNC / RPP], Blo[DMA ? 1 : BNC * U + BNC / RPP];
+  // DMA stages: [stage][Ahi SA | Alo SA | Bhi SB | Blo SB]
+  constexpr int STG = 2 * (SA + SB);
+  __shared__ u32x4 Sd[DMA ? 2 * STG : 1];
+  auto unit = [](int row, int g) {
+    if constexpr (DMA)
+      return U * row + (g ^ ((row / RPP) % U));
+    else
+      return U * row + row / RPP + g;
+  };
 
   const int64_t M = int64_t(1) << d.m, N = int64_t(1) << d.n, K = int64_t(1) << d.k;
   int64_t b, bm, bn;
@@ -387,7 +409,8 @@ __global__ __launch_bounds__(256, (BM * BNC >= 16384 && BKC >= 32) ? 1 : (BM * B
   const u32x4* B = reinterpret_cast<const u32x4*>(d.B + b * d.sB + bn * BNC * K);
   float2* Cc = d.C + b * d.sC;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index is uniform: keep it scalar so that per-wave choices branch on SGPRs
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave >> 1, wn = wave & 1;
   const int h = lane >> 5, i = lane & 31;
 
@@ -462,12 +485,59 @@ __global__ __launch_bounds__(256, (BM * BNC >= 16384 && BKC >= 32) ? 1 : (BM * B
   const int arow0 = wm * C::WM + i;
   const int bcol0 = wn * C::WNC + i;
 
-  load(0);
+  // DMA: slot t (64 units) of a stage -> part array and offset; lane i
+  // fetches the chunk that belongs at unit 64 q + i of that array
+  auto dma = [&](int stage, int64_t k0) {
+    constexpr int T = STG / 64;
+#pragma unroll
+    for (int j = 0; j < T / 4; ++j) {
+      const int t = wave + 4 * j;
+      const int tA = SA / 64, tB = SB / 64;
+      int q, lo;
+      const u32x4* src;
+      int base;
+      if (t < 2 * tA) {
+        lo = t >= tA;
+        q = t - lo * tA;
+        src = A;
+        base = lo * SA;
+      } else {
+        const int tb = t - 2 * tA;
+        lo = tb >= tB;
+        q = tb - lo * tB;
+        src = B;
+        base = 2 * SA + lo * SB;
+      }
+      const int pu = 64 * q + lane;
+      const int row = pu / U, g = (pu % U) ^ ((row / RPP) % U);
+      __builtin_amdgcn_global_load_lds(
+          (const void*)(src + ((int64_t)row * (K >> 1) + (k0 >> 1) + 2 * g + lo)),
+          (__attribute__((address_space(3))) void*)(Sd + stage * STG + base + 64 * q), 16, 0, 0);
+    }
+  };
+
+  if constexpr (DMA) dma(0, 0); else load(0);
   for (int64_t k0 = 0; k0 < K; k0 += BKC) {
-    __syncthreads();
-    stash();
-    __syncthreads();
-    if (k0 + BKC < K) load(k0 + BKC);
+    const u32x4 *SAh, *SAl, *SBh, *SBl;
+    if constexpr (DMA) {
+      const int stage = (int)((k0 / BKC) & 1);
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies into the stage have landed
+      __syncthreads();                // everyone's have, and the other stage is free
+      if (k0 + BKC < K) dma(stage ^ 1, k0 + BKC);
+      SAh = Sd + stage * STG;
+      SAl = SAh + SA;
+      SBh = SAh + 2 * SA;
+      SBl = SBh + SB;
+    } else {
+      __syncthreads();
+      stash();
+      __syncthreads();
+      if (k0 + BKC < K) load(k0 + BKC);
+      SAh = Ahi;
+      SAl = Alo;
+      SBh = Bhi;
+      SBl = Blo;
+    }
 #pragma unroll
     for (int ch = 0; ch < BKC / 8; ++ch) {
       const int gl = 2 * ch + h;  // this lane's group: 8 k' = 4 complex
@@ -475,14 +545,14 @@ __global__ __launch_bounds__(256, (BM * BNC >= 16384 && BKC >= 32) ? 1 : (BM * B
 #pragma unroll
       for (int x = 0; x < C::TM; ++x) {
         int o = unit(arow0 + 32 * x, gl);
-        ah[x] = Ahi[o];
-        al[x] = Alo[o];
+        ah[x] = SAh[o];
+        al[x] = SAl[o];
       }
 #pragma unroll
       for (int y = 0; y < C::TN; ++y) {
         int o = unit(bcol0 + 32 * y, gl);
-        u32x4 bh = Bhi[o];
-        u32x4 bl = Blo[o];
+        u32x4 bh = SBh[o];
+        u32x4 bl = SBl[o];
         u32x4 bs = BF ? bh : times2048(bh);
         u32x4 rh = bform(bh, false), ih = bform(bh, true);
         u32x4 rl = bform(bl, false), il = bform(bl, true);
@@ -550,6 +620,10 @@ const CfgInfo kSplitCfgs[] = {
     {64, 64, 16, "split_64x64x16"},     {128, 64, 32, "split_128x64x32"}, {128, 64, 64, "split_128x64x64"},
     {64, 64, 8, "split_64x64x8"},       {128, 128, 32, "split_128x128x32"}, {64, 64, 32, "split_64x64x32"},
     {64, 128, 32, "split_64x128x32"},
+    // operand tiles staged by global_load_lds, two LDS stages
+    {128, 128, 16, "split_dma_128x128x16"}, {128, 64, 16, "split_dma_128x64x16"},
+    {64, 128, 16, "split_dma_64x128x16"},   {64, 64, 16, "split_dma_64x64x16"},
+    {64, 64, 8, "split_dma_64x64x8"},
 };
 constexpr int kNumSplit = sizeof(kSplitCfgs) / sizeof(kSplitCfgs[0]);
 
@@ -559,13 +633,13 @@ void run(const GemmDesc& d, hipStream_t st) {
   hipLaunchKernelGGL((k_cgemm_c64<BM, BNC, BKC>), dim3((unsigned)tiles), dim3(256), 0, st, d);
 }
 
-template <int BM, int BNC, int BKC>
+template <int BM, int BNC, int BKC, bool DMA = false>
 void run_split(const GemmDesc& d, bool bf, hipStream_t st) {
   int64_t tiles = ((int64_t(1) << d.m) / BM) * ((int64_t(1) << d.n) / BNC) * d.nb;
   if (bf)
-    hipLaunchKernelGGL((k_cgemm_split<BM, BNC, BKC, true>), dim3((unsigned)tiles), dim3(256), 0, st, d);
+    hipLaunchKernelGGL((k_cgemm_split<BM, BNC, BKC, true, DMA>), dim3((unsigned)tiles), dim3(256), 0, st, d);
   else
-    hipLaunchKernelGGL((k_cgemm_split<BM, BNC, BKC, false>), dim3((unsigned)tiles), dim3(256), 0, st, d);
+    hipLaunchKernelGGL((k_cgemm_split<BM, BNC, BKC, false, DMA>), dim3((unsigned)tiles), dim3(256), 0, st, d);
 }
 
 const CfgInfo& info_of(int cfg, int mode) { return mode == LTN_C64 ? kCfgs[cfg] : kSplitCfgs[cfg]; }
@@ -612,6 +686,11 @@ void launch_cgemm(const GemmDesc& d, int mode, hipStream_t st) {
       case 7: run_split<128, 128, 32>(d, bf, st); break;
       case 8: run_split<64, 64, 32>(d, bf, st); break;
       case 9: run_split<64, 128, 32>(d, bf, st); break;
+      case 10: run_split<128, 128, 16, true>(d, bf, st); break;
+      case 11: run_split<128, 64, 16, true>(d, bf, st); break;
+      case 12: run_split<64, 128, 16, true>(d, bf, st); break;
+      case 13: run_split<64, 64, 16, true>(d, bf, st); break;
+      case 14: run_split<64, 64, 8, true>(d, bf, st); break;
     }
     return;
   }

@@ -1,7 +1,7 @@
 """Every kernel a step can run, forced step by step through
 ltn_set_step_kernel: narrow-step kernel in both operand roles, generic
 kernel with 1, 8 and 64 threads per output, complex64 MFMA tiles, and the
-split tiles in the split modes. Each forced plan must reproduce the
+split tiles (register- and DMA-staged) in the split modes. Each forced plan must reproduce the
 brute-force state-vector amplitudes (complex64 <= 1e-4, split <= 5e-4)."""
 import numpy as np
 import pytest
@@ -17,8 +17,10 @@ VARIANTS = {
     "generic_tk1": [(0, -1, 0, 1)],
     "generic_tk8": [(0, -1, 0, 8)],
     "generic_tk64": [(0, -1, 0, 64)],
-    "mfma_c64": [(1, c, s, 1) for s in (0, 1) for c in range(10)],
-    "mfma_split": [(2, c, s, 1) for s in (0, 1) for c in range(10)],
+    "mfma_c64": [(1, c, s, 1) for s in (0, 1) for c in range(16)],
+    "mfma_split": [(2, c, s, 1) for s in (0, 1) for c in range(16)],
+    # split tiles staged by global_load_lds (configurations 10-14)
+    "mfma_split_dma": [(2, c, s, 1) for s in (0, 1) for c in range(10, 15)],
 }
 
 
@@ -51,7 +53,7 @@ def prepared_fat():
 @pytest.mark.parametrize("variant", list(VARIANTS))
 def test_forced_kernel_variant(torch, prepared, prepared_fat, mode, variant):
     import paper_2205_00393_amd as P
-    if variant == "mfma_split" and mode == "c64":
+    if variant.startswith("mfma_split") and mode == "c64":
         pytest.skip("split tiles need a split mode")
     w, pr, ref = prepared_fat if variant.startswith("mfma") else prepared
     plan = pr.plan()
