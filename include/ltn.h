@@ -392,12 +392,13 @@ ltn_status ltn_profile_steps(ltn_plan* plan, uint64_t first_slice, int32_t mode,
  * transposition into the GEMM's store):
  *     out[b][y] = in[b][x]   with bit perm[j] of y equal to bit j of x
  * (bit 0 = fastest-varying). d_in / d_out: device complex64 arrays of
- * batch * 2^rank elements, tensor b at offset b * 2^rank; they must not
- * overlap. perm: host array of rank entries, a permutation of 0..rank-1.
- * Staged through LDS tiles that cover the lowest 5 bits of both sides, so
- * reads and writes are coalesced. Asynchronous on `stream` (hipStream_t as
- * void*; NULL = default stream). Errors: LTN_E_INVALID (rank > 40, perm not
- * a permutation, in == out, batch < 1). */
+ * batch * 2^rank elements, tensor b at offset b * 2^rank, 16-byte aligned
+ * when rank >= 1; they must not overlap. perm: host array of rank entries,
+ * a permutation of 0..rank-1. Staged through LDS tiles that cover the
+ * lowest 5 bits of both sides, so reads and writes are coalesced (16 bytes
+ * per lane). Asynchronous on `stream` (hipStream_t as void*; NULL = default
+ * stream). Errors: LTN_E_INVALID (rank > 40, perm not a permutation,
+ * in == out, batch < 1, a buffer not 16-byte aligned). */
 ltn_status ltn_permute(const void* d_in, void* d_out, int32_t rank, const int32_t* perm,
                        int64_t batch, void* stream);
 

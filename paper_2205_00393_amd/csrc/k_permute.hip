@@ -24,13 +24,17 @@ __device__ __forceinline__ uint64_t spread(uint64_t v, const int8_t* pos, int n)
 }
 
 // Bit maps are linear in the bits, so each tile-local map is the OR of a
-// table over the low 6 tile bits and one over the high 6. Every thread
-// handles tile elements tid + 256 i (i < 16): their offsets are fixed per
-// thread and computed once; a block's 16 loads are issued back to back.
+// table over the low 6 tile bits and one over the high 6. Source bit 0 and
+// destination bit 0 are always tile bits (the lowest of each order), so
+// tile elements 2 j and 2 j + 1 are neighbours in HBM on both sides: every
+// thread moves pairs j = tid + 256 i (i < 8) with one 16-byte load and one
+// 16-byte store; their offsets are fixed per thread and computed once, and a
+// block's 8 loads are issued back to back.
 // LDS slot of tile element l: l with its low 5 bits XORed by swz_tab[l >> 5],
 // chosen on the host so that the 32 elements one half-wave reads in
 // destination order fall into 32 distinct bank pairs.
-constexpr int kThreads = 256, kPer = (1 << kTileBits) / kThreads;
+constexpr int kThreads = 256, kPer = (1 << kTileBits) / kThreads, kPairs = kPer / 2;
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
 // Elements are moved as 64-bit words (pure data movement, bit-exact); the
 // conjugating variant flips the sign bit of each imaginary part.
@@ -63,39 +67,69 @@ __global__ __launch_bounds__(kThreads) void k_permute(const uint64_t* __restrict
   const int nt = 1 << d.n_tile;
   const int lomask = (1 << nlo) - 1;
   const int tid = threadIdx.x;
-  uint64_t soff[kPer], doff[kPer];
-  int wslot[kPer], rslot[kPer];
+  const int64_t per = int64_t(1) << d.rank;
+  const int64_t outer = int64_t(1) << d.n_outer;
+  const uint64_t flip = CONJ ? (1ull << 63) : 0ull;
+  if (nt < 2) {
+    // rank-0 tensors: one element per batch entry
+    for (int64_t blk = blockIdx.x * (int64_t)kThreads + tid; blk < d.batch; blk += (int64_t)gridDim.x * kThreads)
+      out[blk] = in[blk] ^ flip;
+    return;
+  }
+  uint64_t soff[kPairs], doff[kPairs];
+  int ws0[kPairs], ws1[kPairs], rs0[kPairs], rs1[kPairs];
+  auto rslot = [&](int l) {
+    const int t = map_lo[l & lomask] | map_hi[l >> nlo];
+    return t ^ swz_tab[t >> 5];
+  };
 #pragma unroll
-  for (int i = 0; i < kPer; ++i) {
-    const int l = tid + kThreads * i;
+  for (int i = 0; i < kPairs; ++i) {
+    const int l = 2 * (tid + kThreads * i);
     if (l < nt) {
       soff[i] = src_lo[l & lomask] | src_hi[l >> nlo];
       doff[i] = dst_lo[l & lomask] | dst_hi[l >> nlo];
-      wslot[i] = l ^ swz_tab[l >> 5];
-      const int t = map_lo[l & lomask] | map_hi[l >> nlo];
-      rslot[i] = t ^ swz_tab[t >> 5];
+      ws0[i] = l ^ swz_tab[l >> 5];
+      ws1[i] = (l + 1) ^ swz_tab[(l + 1) >> 5];
+      rs0[i] = rslot(l);
+      rs1[i] = rslot(l + 1);
     }
   }
-  const int64_t per = int64_t(1) << d.rank;
-  const int64_t outer = int64_t(1) << d.n_outer;
-  for (int64_t blk = blockIdx.x; blk < outer * d.batch; blk += gridDim.x) {
+  // Blocks are persistent (a few per CU, so that the tables above are built
+  // once per block): the next tile's loads are issued as soon as the current
+  // tile sits in LDS, and overlap its LDS reads and HBM writes.
+  const int64_t tiles = outer * d.batch;
+  auto fetch = [&](int64_t blk, u64x2* w) {
     const int64_t b = blk / outer, o = blk % outer;
     const uint64_t* src = in + b * per + spread((uint64_t)o, d.outer_src, d.n_outer);
+#pragma unroll
+    for (int i = 0; i < kPairs; ++i)
+      if (2 * (tid + kThreads * i) < nt)
+        w[i] = __builtin_nontemporal_load(reinterpret_cast<const u64x2*>(src + soff[i]));
+  };
+  u64x2 nx[kPairs];
+  if (blockIdx.x < tiles) fetch(blockIdx.x, nx);
+  for (int64_t blk = blockIdx.x; blk < tiles; blk += gridDim.x) {
+    const int64_t b = blk / outer, o = blk % outer;
     uint64_t* dst = out + b * per + spread((uint64_t)o, d.outer_dst, d.n_outer);
-    uint64_t v[kPer];
+    u64x2 v[kPairs];
 #pragma unroll
-    for (int i = 0; i < kPer; ++i)
-      if (tid + kThreads * i < nt) v[i] = __builtin_nontemporal_load(&src[soff[i]]);
-#pragma unroll
-    for (int i = 0; i < kPer; ++i)
-      if (tid + kThreads * i < nt) tile[wslot[i]] = v[i];
+    for (int i = 0; i < kPairs; ++i)
+      if (2 * (tid + kThreads * i) < nt) {
+        tile[ws0[i]] = nx[i].x;
+        tile[ws1[i]] = nx[i].y;
+      }
     __syncthreads();
+    if (blk + gridDim.x < tiles) fetch(blk + gridDim.x, nx);
 #pragma unroll
-    for (int i = 0; i < kPer; ++i)
-      if (tid + kThreads * i < nt) v[i] = CONJ ? (tile[rslot[i]] ^ (1ull << 63)) : tile[rslot[i]];
+    for (int i = 0; i < kPairs; ++i)
+      if (2 * (tid + kThreads * i) < nt) {
+        v[i].x = tile[rs0[i]] ^ flip;
+        v[i].y = tile[rs1[i]] ^ flip;
+      }
 #pragma unroll
-    for (int i = 0; i < kPer; ++i)
-      if (tid + kThreads * i < nt) __builtin_nontemporal_store(v[i], &dst[doff[i]]);
+    for (int i = 0; i < kPairs; ++i)
+      if (2 * (tid + kThreads * i) < nt)
+        __builtin_nontemporal_store(v[i], reinterpret_cast<u64x2*>(dst + doff[i]));
     __syncthreads();
   }
 }
@@ -103,8 +137,9 @@ __global__ __launch_bounds__(kThreads) void k_permute(const uint64_t* __restrict
 }  // namespace
 
 void launch_permute(const float2* in, float2* out, const PermuteDesc& d, hipStream_t st) {
+  // persistent blocks: 3 per CU on 256 CUs (registers allow 3 waves per SIMD)
   int64_t blocks = (int64_t(1) << d.n_outer) * d.batch;
-  if (blocks > 65536) blocks = 65536;
+  if (blocks > 768) blocks = 768;
   if (d.flip)
     hipLaunchKernelGGL(k_permute<true>, dim3((unsigned)blocks), dim3(kThreads), 0, st,
                        reinterpret_cast<const uint64_t*>(in), reinterpret_cast<uint64_t*>(out), d);

@@ -1091,6 +1091,8 @@ extern "C" ltn_status ltn_permute(const void* d_in, void* d_out, int32_t rank, c
     require(rank >= 0 && rank <= 40, "rank must be in 0..40");
     require(batch >= 1, "batch must be >= 1");
     require(rank == 0 || perm != nullptr, "perm is NULL");
+    require(rank == 0 || ((uintptr_t)d_in % 16 == 0 && (uintptr_t)d_out % 16 == 0),
+            "d_in and d_out must be 16-byte aligned");
     for (int j = 0; j < rank; ++j) require(perm[j] >= 0 && perm[j] < rank, "perm is not a permutation");
     std::vector<char> seen(rank, 0);
     for (int j = 0; j < rank; ++j) {

@@ -34,3 +34,20 @@ def test_error_reporting_without_gpu():
     assert st == -1 and "NULL" in L.ltn_last_error().decode()
     # device entry points refuse an unbound or NULL plan before touching HIP
     assert L.ltn_execute_range(None, 0, 1, 0, None) == -5
+
+
+def test_permute_argument_checks_without_gpu():
+    """ltn_permute rejects bad arguments on the host, before any HIP call:
+    a non-permutation, in == out, and buffers that are not 16-byte aligned
+    (the kernel moves 16-byte pairs). The pointers are never dereferenced."""
+    import ctypes as C
+    L = _lib.lib()
+    perm = (C.c_int32 * 3)(2, 0, 1)
+    bad = (C.c_int32 * 3)(0, 0, 1)
+    assert L.ltn_permute(C.c_void_p(4096), C.c_void_p(8192), 3, bad, 1, None) == -1
+    assert "permutation" in L.ltn_last_error().decode()
+    assert L.ltn_permute(C.c_void_p(4096), C.c_void_p(4096), 3, perm, 1, None) == -1
+    assert L.ltn_permute(C.c_void_p(4104), C.c_void_p(8192), 3, perm, 1, None) == -1
+    assert "aligned" in L.ltn_last_error().decode()
+    assert L.ltn_permute(C.c_void_p(4096), C.c_void_p(8200), 3, perm, 1, None) == -1
+    assert "aligned" in L.ltn_last_error().decode()
