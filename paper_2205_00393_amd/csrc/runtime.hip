@@ -54,6 +54,9 @@ struct ltn_plan_impl {
   std::vector<char> needs_grad;
   hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
   hipGraph_t graph_src[3] = {nullptr, nullptr, nullptr};
+  // gradients, full batches: recomputed forward and adjoint sweep
+  hipGraphExec_t ggraph[2] = {nullptr, nullptr};
+  hipGraph_t ggraph_src[2] = {nullptr, nullptr};
   std::vector<uint64_t> host_ids;
 };
 
@@ -335,31 +338,41 @@ void check_launch() {
   if (e != hipSuccess) fail(LTN_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
 }
 
+// Launch the work `enqueue` issues as one graph on the bound stream,
+// capturing it (on a stream of our own) the first time. The captured
+// kernels keep their arguments, so only work whose pointers and shapes are
+// fixed for the bound workspace goes in.
+template <typename F>
+void launch_captured(ltn_plan* p, hipGraphExec_t& exec, hipGraph_t& src, F&& enqueue) {
+  auto& r = *p->rt;
+  if (!exec) {
+    if (!r.cap) HIPCHECK(hipStreamCreateWithFlags(&r.cap, hipStreamNonBlocking));
+    hipGraph_t g;
+    hipStream_t bound = r.st;
+    r.st = r.cap;
+    hipError_t e = hipStreamBeginCapture(r.cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      try {
+        enqueue();
+      } catch (...) {
+        r.st = bound;
+        (void)hipStreamEndCapture(r.cap, &g);
+        throw;
+      }
+      e = hipStreamEndCapture(r.cap, &g);
+    }
+    r.st = bound;
+    if (e != hipSuccess) fail(LTN_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    HIPCHECK(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+    src = g;
+  }
+  HIPCHECK(hipGraphLaunch(exec, r.st));
+}
+
 void run_batch(ltn_plan* p, int nb, int mode, double* out) {
   auto& r = *p->rt;
   if (nb == r.B) {
-    if (!r.graph[mode]) {
-      if (!r.cap) HIPCHECK(hipStreamCreateWithFlags(&r.cap, hipStreamNonBlocking));
-      hipGraph_t g;
-      hipStream_t bound = r.st;
-      r.st = r.cap;
-      hipError_t e = hipStreamBeginCapture(r.cap, hipStreamCaptureModeThreadLocal);
-      if (e == hipSuccess) {
-        try {
-          enqueue_forward(p, nb, false, mode);
-        } catch (...) {
-          r.st = bound;
-          (void)hipStreamEndCapture(r.cap, &g);
-          throw;
-        }
-        e = hipStreamEndCapture(r.cap, &g);
-      }
-      r.st = bound;
-      if (e != hipSuccess) fail(LTN_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
-      HIPCHECK(hipGraphInstantiate(&r.graph[mode], g, nullptr, nullptr, 0));
-      r.graph_src[mode] = g;
-    }
-    HIPCHECK(hipGraphLaunch(r.graph[mode], r.st));
+    launch_captured(p, r.graph[mode], r.graph_src[mode], [&] { enqueue_forward(p, nb, false, mode); });
   } else {
     enqueue_forward(p, nb, false, mode);
   }
@@ -383,6 +396,10 @@ void runtime_free(ltn_plan* p) {
   for (int m = 0; m < 3; ++m) {
     if (p->rt->graph[m]) (void)hipGraphExecDestroy(p->rt->graph[m]);
     if (p->rt->graph_src[m]) (void)hipGraphDestroy(p->rt->graph_src[m]);
+  }
+  for (int m = 0; m < 2; ++m) {
+    if (p->rt->ggraph[m]) (void)hipGraphExecDestroy(p->rt->ggraph[m]);
+    if (p->rt->ggraph_src[m]) (void)hipGraphDestroy(p->rt->ggraph_src[m]);
   }
   if (p->rt->cap) (void)hipStreamDestroy(p->rt->cap);
   delete p->rt;
@@ -646,6 +663,105 @@ static const float2* enqueue_perm(ltn_plan* p, const float2* in, float2* out,
   return out;
 }
 
+// Adjoint sweep of one batch (steps in reverse order), then the leaf
+// cotangents accumulated into the per-leaf FP64 sums. Every pointer is in
+// the bound workspace, so a full batch can run from a captured graph.
+static void enqueue_backward(ltn_plan* p, int nb) {
+  auto& r = *p->rt;
+  double* lg = reinterpret_cast<double*>(r.ws + r.lay.leafgrad);
+  const GatherDesc* gcot = reinterpret_cast<const GatherDesc*>(r.ws + r.lay.gd_gcot);
+  const uint64_t* dids = reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids);
+  for (int s = (int)p->steps.size() - 1; s >= 0; --s) {
+    const StepPlan& sp = p->steps[s];
+    if (!r.needs_grad[sp.out]) continue;
+    const TensorPlan &ta = p->tensors[sp.a], &tb = p->tensors[sp.b], &tc = p->tensors[sp.out];
+    const uint64_t cm = sp.c_mask_a;
+    // small steps: one generic kernel per operand, reading the operands
+    // in place (strided) and conjugating the second one
+    if (sp.m + sp.n + sp.k <= 16) {
+      const uint64_t full = (1ull << (sp.m + sp.n)) - 1;
+      if (r.needs_grad[sp.a]) {
+        GenericDesc g{};
+        g.P = arena_ptr(p, tc.gcot);
+        g.Q = arena_ptr(p, tb.goff);
+        g.out = arena_ptr(p, ta.gcot);
+        g.sP = int64_t(1) << tc.rank;
+        g.sQ = int64_t(1) << tb.rank;
+        g.sO = int64_t(1) << ta.rank;
+        g.xb = sp.m;
+        g.yb = sp.k;
+        g.zb = sp.n;
+        g.px = cm;
+        g.pz = ~cm & full;
+        g.qy = (1ull << sp.k) - 1;
+        g.qz = ((1ull << sp.n) - 1) << sp.k;
+        g.ox = ((1ull << sp.m) - 1) << sp.k;
+        g.oy = (1ull << sp.k) - 1;
+        g.conjQ = 1;
+        g.nb = nb;
+        launch_generic(g, default_tk(sp.n, (1ull << (sp.m + sp.k)) * (uint64_t)nb), r.st);
+      }
+      if (r.needs_grad[sp.b]) {
+        GenericDesc g{};
+        g.P = arena_ptr(p, tc.gcot);
+        g.Q = arena_ptr(p, ta.goff);
+        g.out = arena_ptr(p, tb.gcot);
+        g.sP = int64_t(1) << tc.rank;
+        g.sQ = int64_t(1) << ta.rank;
+        g.sO = int64_t(1) << tb.rank;
+        g.xb = sp.n;
+        g.yb = sp.k;
+        g.zb = sp.m;
+        g.px = ~cm & full;
+        g.pz = cm;
+        g.qy = (1ull << sp.k) - 1;
+        g.qz = ((1ull << sp.m) - 1) << sp.k;
+        g.ox = ((1ull << sp.n) - 1) << sp.k;
+        g.oy = (1ull << sp.k) - 1;
+        g.conjQ = 1;
+        g.nb = nb;
+        launch_generic(g, default_tk(sp.m, (1ull << (sp.n + sp.k)) * (uint64_t)nb), r.st);
+      }
+      continue;
+    }
+    // adjoint products in the forward form: the output cotangent
+    // and the other operand are permuted so that the summed bits are
+    // lowest (and the operand conjugated), then one GEMM per operand
+    float2* Xs = reinterpret_cast<float2*>(r.ws + r.lay.gscr_c);
+    float2* Ys = reinterpret_cast<float2*>(r.ws + r.lay.gscr);
+    const int rc = sp.m + sp.n;
+    // positions of the m bits (in order) and the n bits of the output
+    std::vector<int> mpos, npos;
+    for (int j = 0; j < rc; ++j) ((cm >> j) & 1 ? mpos : npos).push_back(j);
+    if (r.needs_grad[sp.a]) {
+      // dA[m][k] = sum_n dC[merge(m, n)] conj(B[n][k])
+      std::vector<int32_t> pc(rc), pb(sp.k + sp.n);
+      for (int i = 0; i < sp.m; ++i) pc[mpos[i]] = sp.n + i;
+      for (int i = 0; i < sp.n; ++i) pc[npos[i]] = i;
+      for (int j = 0; j < sp.k; ++j) pb[j] = sp.n + j;
+      for (int i = 0; i < sp.n; ++i) pb[sp.k + i] = i;
+      const float2* X = enqueue_perm(p, arena_ptr(p, tc.gcot), Xs, pc, nb, false);
+      enqueue_perm(p, arena_ptr(p, tb.goff), Ys, pb, nb, true);
+      enqueue_nt(p, X, int64_t(1) << rc, Ys, int64_t(1) << tb.rank, arena_ptr(p, ta.gcot),
+                 int64_t(1) << ta.rank, sp.m, sp.n, sp.k, ((1ull << sp.m) - 1) << sp.k, nb);
+    }
+    if (r.needs_grad[sp.b]) {
+      // dB[n][k] = sum_m dC[merge(m, n)] conj(A[m][k])
+      std::vector<int32_t> pc(rc), pa(sp.k + sp.m);
+      for (int i = 0; i < sp.m; ++i) pc[mpos[i]] = i;
+      for (int i = 0; i < sp.n; ++i) pc[npos[i]] = sp.m + i;
+      for (int j = 0; j < sp.k; ++j) pa[j] = sp.m + j;
+      for (int i = 0; i < sp.m; ++i) pa[sp.k + i] = i;
+      const float2* X = enqueue_perm(p, arena_ptr(p, tc.gcot), Xs, pc, nb, false);
+      enqueue_perm(p, arena_ptr(p, ta.goff), Ys, pa, nb, true);
+      enqueue_nt(p, X, int64_t(1) << rc, Ys, int64_t(1) << ta.rank, arena_ptr(p, tb.gcot),
+                 int64_t(1) << tb.rank, sp.n, sp.m, sp.k, ((1ull << sp.n) - 1) << sp.k, nb);
+    }
+  }
+  launch_leaf_cot_accumulate(reinterpret_cast<const ParamLeaf*>(r.ws + r.lay.pl), r.n_pl, gcot,
+                             arena_ptr(p, 0), dids, nb, lg, r.st);
+}
+
 extern "C" ltn_status ltn_execute_grad(ltn_plan* p, const uint64_t* ids, uint64_t n, int32_t mode,
                                        const void* d_cot, void* d_out, double* d_angle_grad) {
   return guarded([&] {
@@ -660,106 +776,25 @@ extern "C" ltn_status ltn_execute_grad(ltn_plan* p, const uint64_t* ids, uint64_
       for (uint64_t i = 0; i < n; ++i) require(ids[i] < (1ull << ns), "slice id is not below 2^|S|");
     double* lg = reinterpret_cast<double*>(r.ws + r.lay.leafgrad);
     launch_fill_zero(lg, al((size_t)r.n_pl * 64), r.st);
-    const GatherDesc* gcot = reinterpret_cast<const GatherDesc*>(r.ws + r.lay.gd_gcot);
     const uint64_t* dids = reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids);
+    // full batches run the recomputed forward and the adjoint sweep from two
+    // captured graphs; the cotangent and output pointers stay outside them
     for (uint64_t off = 0; off < n; off += (uint64_t)r.B) {
       int nb = (int)std::min<uint64_t>((uint64_t)r.B, n - off);
       set_ids(p, ids + off, 0, nb, false);
-      enqueue_forward(p, nb, true, LTN_C64);
+      if (nb == r.B)
+        launch_captured(p, r.ggraph[0], r.ggraph_src[0], [&] { enqueue_forward(p, nb, true, LTN_C64); });
+      else
+        enqueue_forward(p, nb, true, LTN_C64);
       if (d_out) enqueue_reduce(p, nb, true, reinterpret_cast<double*>(d_out));
       const TensorPlan& root = p->tensors[p->root];
       launch_root_cotangent(reinterpret_cast<const double*>(d_cot), root.rank, p->out_mask,
                             r.sl_bits.data(), r.out_bits.data(), (int)r.sl_bits.size(), dids, nb,
                             arena_ptr(p, root.gcot), r.st);
-      for (int s = (int)p->steps.size() - 1; s >= 0; --s) {
-        const StepPlan& sp = p->steps[s];
-        if (!r.needs_grad[sp.out]) continue;
-        const TensorPlan &ta = p->tensors[sp.a], &tb = p->tensors[sp.b], &tc = p->tensors[sp.out];
-        const uint64_t cm = sp.c_mask_a;
-        // small steps: one generic kernel per operand, reading the operands
-        // in place (strided) and conjugating the second one
-        if (sp.m + sp.n + sp.k <= 16) {
-          const uint64_t full = (1ull << (sp.m + sp.n)) - 1;
-          if (r.needs_grad[sp.a]) {
-            GenericDesc g{};
-            g.P = arena_ptr(p, tc.gcot);
-            g.Q = arena_ptr(p, tb.goff);
-            g.out = arena_ptr(p, ta.gcot);
-            g.sP = int64_t(1) << tc.rank;
-            g.sQ = int64_t(1) << tb.rank;
-            g.sO = int64_t(1) << ta.rank;
-            g.xb = sp.m;
-            g.yb = sp.k;
-            g.zb = sp.n;
-            g.px = cm;
-            g.pz = ~cm & full;
-            g.qy = (1ull << sp.k) - 1;
-            g.qz = ((1ull << sp.n) - 1) << sp.k;
-            g.ox = ((1ull << sp.m) - 1) << sp.k;
-            g.oy = (1ull << sp.k) - 1;
-            g.conjQ = 1;
-            g.nb = nb;
-            launch_generic(g, default_tk(sp.n, (1ull << (sp.m + sp.k)) * (uint64_t)nb), r.st);
-          }
-          if (r.needs_grad[sp.b]) {
-            GenericDesc g{};
-            g.P = arena_ptr(p, tc.gcot);
-            g.Q = arena_ptr(p, ta.goff);
-            g.out = arena_ptr(p, tb.gcot);
-            g.sP = int64_t(1) << tc.rank;
-            g.sQ = int64_t(1) << ta.rank;
-            g.sO = int64_t(1) << tb.rank;
-            g.xb = sp.n;
-            g.yb = sp.k;
-            g.zb = sp.m;
-            g.px = ~cm & full;
-            g.pz = cm;
-            g.qy = (1ull << sp.k) - 1;
-            g.qz = ((1ull << sp.m) - 1) << sp.k;
-            g.ox = ((1ull << sp.n) - 1) << sp.k;
-            g.oy = (1ull << sp.k) - 1;
-            g.conjQ = 1;
-            g.nb = nb;
-            launch_generic(g, default_tk(sp.m, (1ull << (sp.n + sp.k)) * (uint64_t)nb), r.st);
-          }
-          continue;
-        }
-        // adjoint products in the forward form: the output cotangent
-        // and the other operand are permuted so that the summed bits are
-        // lowest (and the operand conjugated), then one GEMM per operand
-        float2* Xs = reinterpret_cast<float2*>(r.ws + r.lay.gscr_c);
-        float2* Ys = reinterpret_cast<float2*>(r.ws + r.lay.gscr);
-        const int rc = sp.m + sp.n;
-        // positions of the m bits (in order) and the n bits of the output
-        std::vector<int> mpos, npos;
-        for (int j = 0; j < rc; ++j) ((cm >> j) & 1 ? mpos : npos).push_back(j);
-        if (r.needs_grad[sp.a]) {
-          // dA[m][k] = sum_n dC[merge(m, n)] conj(B[n][k])
-          std::vector<int32_t> pc(rc), pb(sp.k + sp.n);
-          for (int i = 0; i < sp.m; ++i) pc[mpos[i]] = sp.n + i;
-          for (int i = 0; i < sp.n; ++i) pc[npos[i]] = i;
-          for (int j = 0; j < sp.k; ++j) pb[j] = sp.n + j;
-          for (int i = 0; i < sp.n; ++i) pb[sp.k + i] = i;
-          const float2* X = enqueue_perm(p, arena_ptr(p, tc.gcot), Xs, pc, nb, false);
-          enqueue_perm(p, arena_ptr(p, tb.goff), Ys, pb, nb, true);
-          enqueue_nt(p, X, int64_t(1) << rc, Ys, int64_t(1) << tb.rank, arena_ptr(p, ta.gcot),
-                     int64_t(1) << ta.rank, sp.m, sp.n, sp.k, ((1ull << sp.m) - 1) << sp.k, nb);
-        }
-        if (r.needs_grad[sp.b]) {
-          // dB[n][k] = sum_m dC[merge(m, n)] conj(A[m][k])
-          std::vector<int32_t> pc(rc), pa(sp.k + sp.m);
-          for (int i = 0; i < sp.m; ++i) pc[mpos[i]] = i;
-          for (int i = 0; i < sp.n; ++i) pc[npos[i]] = sp.m + i;
-          for (int j = 0; j < sp.k; ++j) pa[j] = sp.m + j;
-          for (int i = 0; i < sp.m; ++i) pa[sp.k + i] = i;
-          const float2* X = enqueue_perm(p, arena_ptr(p, tc.gcot), Xs, pc, nb, false);
-          enqueue_perm(p, arena_ptr(p, ta.goff), Ys, pa, nb, true);
-          enqueue_nt(p, X, int64_t(1) << rc, Ys, int64_t(1) << ta.rank, arena_ptr(p, tb.gcot),
-                     int64_t(1) << tb.rank, sp.n, sp.m, sp.k, ((1ull << sp.n) - 1) << sp.k, nb);
-        }
-      }
-      launch_leaf_cot_accumulate(reinterpret_cast<const ParamLeaf*>(r.ws + r.lay.pl), r.n_pl, gcot,
-                                 arena_ptr(p, 0), dids, nb, lg, r.st);
+      if (nb == r.B)
+        launch_captured(p, r.ggraph[1], r.ggraph_src[1], [&] { enqueue_backward(p, nb); });
+      else
+        enqueue_backward(p, nb);
       check_launch();
     }
     launch_u3_adjoint(reinterpret_cast<const ParamLeaf*>(r.ws + r.lay.pl), r.n_pl,
@@ -835,6 +870,12 @@ void drop_graphs(ltn_plan* p) {
     if (r.graph_src[m]) (void)hipGraphDestroy(r.graph_src[m]);
     r.graph[m] = nullptr;
     r.graph_src[m] = nullptr;
+  }
+  for (int m = 0; m < 2; ++m) {
+    if (r.ggraph[m]) (void)hipGraphExecDestroy(r.ggraph[m]);
+    if (r.ggraph_src[m]) (void)hipGraphDestroy(r.ggraph_src[m]);
+    r.ggraph[m] = nullptr;
+    r.ggraph_src[m] = nullptr;
   }
 }
 

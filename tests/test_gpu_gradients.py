@@ -68,3 +68,45 @@ def test_rqc20_gradient(torch):
     sub = ref["subset"]
     assert rel_l2(g[sub], ref["finite_diff"]) < 1e-3
     assert rel_l2(g[sub], ref["param_shift"]) < 1e-3
+
+
+def test_gradient_graph_replays_match_eager(torch):
+    """Full gradient batches run from two captured graphs (recomputed
+    forward, adjoint sweep). A plan bound with batch 4 replays them 8 times
+    per call on 32 slices; three calls (cotangents a, b, a), with other work
+    and synchronisations between them, must each match a plan whose single
+    batch of 32 is below its bound size and so runs eagerly (to FP32
+    reordering: kernel choices depend on the batch size), and the repeated
+    cotangent must give bit-identical gradients."""
+    import paper_2205_00393_amd as P
+    w = _small_workload()
+    pr = P.prepare(w, alphas=(0.5, 1.0), taus=(0.0, 0.3), n_seeds=3)
+    ids = [pr.slice_of_bitstring(int(x)) for x in w.bitstrings]
+    angles = torch.tensor(w.circuit.angles(), dtype=torch.float64, device="cuda")
+    graphed, eager = pr.plan(), pr.plan()
+    assert graphed.bind(batch=4, grad=True, budget_bytes=1 << 30) == 4
+    assert eager.bind(batch=64, grad=True, budget_bytes=1 << 30) > len(ids)
+    graphed.set_params(angles)
+    eager.set_params(angles)
+    gen = torch.Generator(device="cpu").manual_seed(11)
+    n_out = 1 << graphed.info()["n_open"]
+    cots = [torch.complex(torch.randn(n_out, generator=gen, dtype=torch.float64),
+                          torch.randn(n_out, generator=gen, dtype=torch.float64)).cuda()
+            for _ in range(2)]
+    first = None
+    for call, cot in enumerate([cots[0], cots[1], cots[0]]):
+        out_g, out_e = graphed.new_output(), eager.new_output()
+        g_graph = graphed.execute_grad(ids, cot, out_g)
+        graphed.execute(ids[:3])  # other work on the same plan between replays
+        torch.cuda.synchronize()
+        g_eager = eager.execute_grad(ids, cot, out_e)
+        torch.cuda.synchronize()
+        gg = g_graph.cpu().numpy()
+        err = rel_l2(gg, g_eager.cpu().numpy())
+        err_out = rel_l2(out_g.cpu().numpy(), out_e.cpu().numpy())
+        banner(f"gradient graph replay {call}: rel diff {err:.2e} (outputs {err_out:.2e})")
+        assert err < 1e-5 and err_out < 1e-5
+        if call == 0:
+            first = gg
+        if call == 2:
+            assert np.array_equal(gg, first)
