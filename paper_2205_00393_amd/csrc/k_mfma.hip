@@ -349,10 +349,10 @@ __global__ __launch_bounds__(256) void k_split_convert(const float2* X, float2* 
 // complex columns. MFMA columns are complex outputs: each lane reads its B
 // value once and forms both real-form rows of it, (re, -im) for the real
 // accumulator and (im, re) for the imaginary one.
-template <int BM, int BNC, int BKC>
+template <int BM, int BNC, int BKC, int NWN>
 struct SplitCfg {
   static constexpr int WM = BM / 2, TM = WM / 32;
-  static constexpr int WNC = BNC / 2, TN = WNC / 32;
+  static constexpr int WNC = BNC / NWN, TN = WNC / 32;
   static_assert(TM >= 1 && TN >= 1 && BKC % 8 == 0, "tile too small for the split GEMM");
 };
 
@@ -370,9 +370,15 @@ struct SplitCfg {
 //    that unit U r + (g ^ sw(r)) of a part array holds group g of row r,
 //    sw(r) = (r / (16 / U)) mod U: 16 consecutive rows at one group then fall
 //    on 16 distinct units (all 64 banks) as with the padding.
-template <int BM, int BNC, int BKC, bool BF, bool DMA>
-__global__ __launch_bounds__(256, (BM * BNC >= 16384 && BKC >= 32) ? 1 : (BM * BNC >= 16384 || BKC >= 32 ? 2 : 3)) void k_cgemm_split(GemmDesc d) {
-  using C = SplitCfg<BM, BNC, BKC>;
+//
+// NWN waves along the columns (2 x NWN waves per block): 2 as a rule; 4 with
+// DMA staging puts four waves on each SIMD (two blocks of eight) to hide
+// LDS and barrier latency behind more independent matrix work.
+template <int BM, int BNC, int BKC, bool BF, bool DMA, int NWN = 2>
+__global__ __launch_bounds__(128 * NWN, NWN == 4 ? 2 : ((BM * BNC >= 16384 && BKC >= 32) ? 1 : (BM * BNC >= 16384 || BKC >= 32 ? 2 : 3))) void k_cgemm_split(GemmDesc d) {
+  static_assert(NWN == 2 || (NWN == 4 && DMA), "eight-wave blocks need DMA staging");
+  constexpr int NW = 2 * NWN;  // waves per block
+  using C = SplitCfg<BM, BNC, BKC, NWN>;
   // LDS rows of U 16-byte units (one unit = 4 complex of hi or lo parts);
   // row r starts at unit U r + r / (16 / U), so that 16 consecutive rows at
   // one group (a read pass) and the 16 / U rows x U groups of a store pass
@@ -384,8 +390,8 @@ __global__ __launch_bounds__(256, (BM * BNC >= 16384 && BKC >= 32) ? 1 : (BM * B
   constexpr int RA = (CHA + 255) / 256, RB = (CHB + 255) / 256;
   static_assert(BM % RPP == 0 && BNC % RPP == 0, "tile rows must fill store passes");
   constexpr int SA = BM * U, SB = BNC * U;  // DMA: units per part array and stage
-  static_assert(!DMA || (SA % 64 == 0 && SB % 64 == 0 && ((SA + SB) / 32) % 4 == 0),
-                "DMA staging needs whole 64-unit slots, a multiple of 4 per stage");
+  static_assert(!DMA || (SA % 64 == 0 && SB % 64 == 0 && ((SA + SB) / 32) % NW == 0),
+                "DMA staging needs whole 64-unit slots, a multiple of the wave count per stage");
   __shared__ u32x4 Ahi[DMA ? 1 : BM * U + BM / RPP], Alo[DMA ? 1 : BM * U + BM / RPP];
   __shared__ u32x4 Bhi[DMA ? 1 : BNC * U + BNC / RPP], Blo[DMA ? 1 : BNC * U + BNC / RPP];
   // DMA stages: [stage][Ahi SA | Alo SA | Bhi SB | Blo SB]
@@ -411,7 +417,7 @@ __global__ __launch_bounds__(256, (BM * BNC >= 16384 && BKC >= 32) ? 1 : (BM * B
 
   // the wave index is uniform: keep it scalar so that per-wave choices branch on SGPRs
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / NWN, wn = wave % NWN;
   const int h = lane >> 5, i = lane & 31;
 
   floatx16 are[C::TM][C::TN], aim[C::TM][C::TN];
@@ -490,8 +496,8 @@ __global__ __launch_bounds__(256, (BM * BNC >= 16384 && BKC >= 32) ? 1 : (BM * B
   auto dma = [&](int stage, int64_t k0) {
     constexpr int T = STG / 64;
 #pragma unroll
-    for (int j = 0; j < T / 4; ++j) {
-      const int t = wave + 4 * j;
+    for (int j = 0; j < T / NW; ++j) {
+      const int t = wave + NW * j;
       const int tA = SA / 64, tB = SB / 64;
       int q, lo;
       const u32x4* src;
@@ -624,6 +630,8 @@ const CfgInfo kSplitCfgs[] = {
     {128, 128, 16, "split_dma_128x128x16"}, {128, 64, 16, "split_dma_128x64x16"},
     {64, 128, 16, "split_dma_64x128x16"},   {64, 64, 16, "split_dma_64x64x16"},
     {64, 64, 8, "split_dma_64x64x8"},
+    // eight waves per block (2 x 4), DMA staging
+    {128, 128, 16, "split_dma8w_128x128x16"},
 };
 constexpr int kNumSplit = sizeof(kSplitCfgs) / sizeof(kSplitCfgs[0]);
 
@@ -633,13 +641,13 @@ void run(const GemmDesc& d, hipStream_t st) {
   hipLaunchKernelGGL((k_cgemm_c64<BM, BNC, BKC>), dim3((unsigned)tiles), dim3(256), 0, st, d);
 }
 
-template <int BM, int BNC, int BKC, bool DMA = false>
+template <int BM, int BNC, int BKC, bool DMA = false, int NWN = 2>
 void run_split(const GemmDesc& d, bool bf, hipStream_t st) {
   int64_t tiles = ((int64_t(1) << d.m) / BM) * ((int64_t(1) << d.n) / BNC) * d.nb;
   if (bf)
-    hipLaunchKernelGGL((k_cgemm_split<BM, BNC, BKC, true, DMA>), dim3((unsigned)tiles), dim3(256), 0, st, d);
+    hipLaunchKernelGGL((k_cgemm_split<BM, BNC, BKC, true, DMA, NWN>), dim3((unsigned)tiles), dim3(128 * NWN), 0, st, d);
   else
-    hipLaunchKernelGGL((k_cgemm_split<BM, BNC, BKC, false, DMA>), dim3((unsigned)tiles), dim3(256), 0, st, d);
+    hipLaunchKernelGGL((k_cgemm_split<BM, BNC, BKC, false, DMA, NWN>), dim3((unsigned)tiles), dim3(128 * NWN), 0, st, d);
 }
 
 const CfgInfo& info_of(int cfg, int mode) { return mode == LTN_C64 ? kCfgs[cfg] : kSplitCfgs[cfg]; }
@@ -691,6 +699,7 @@ void launch_cgemm(const GemmDesc& d, int mode, hipStream_t st) {
       case 12: run_split<64, 128, 16, true>(d, bf, st); break;
       case 13: run_split<64, 64, 16, true>(d, bf, st); break;
       case 14: run_split<64, 64, 8, true>(d, bf, st); break;
+      case 15: run_split<128, 128, 16, true, 4>(d, bf, st); break;
     }
     return;
   }

@@ -19,8 +19,8 @@ VARIANTS = {
     "generic_tk64": [(0, -1, 0, 64)],
     "mfma_c64": [(1, c, s, 1) for s in (0, 1) for c in range(16)],
     "mfma_split": [(2, c, s, 1) for s in (0, 1) for c in range(16)],
-    # split tiles staged by global_load_lds (configurations 10-14)
-    "mfma_split_dma": [(2, c, s, 1) for s in (0, 1) for c in range(10, 15)],
+    # split tiles staged by global_load_lds (configurations 10-15)
+    "mfma_split_dma": [(2, c, s, 1) for s in (0, 1) for c in range(10, 16)],
 }
 
 
