@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--path", default="greedy", choices=["greedy", "reconf"],
                     help="path of the headline plan: randomised greedy (the workload's definition) "
                          "or greedy + subtree reconfiguration")
+    ap.add_argument("--reconf-k", type=int, default=None,
+                    help="subtree reconfiguration window (default: 10 for rqc30, 8 for rqc53)")
     ap.add_argument("--path-variant", default="c64,split_bf16",
                     help="modes to time on the reconfigured path as well ('' to skip)")
     ap.add_argument("--no-grad", action="store_true",
@@ -245,8 +247,9 @@ def main():
         return results, facts
 
     pr_seconds = {}
+    reconf_k = args.reconf_k if args.reconf_k is not None else (10 if args.workload == "rqc30" else 8)
     t0 = time.perf_counter()
-    pr = P.prepare(w, reconf_k=8 if args.path == "reconf" else 0)
+    pr = P.prepare(w, reconf_k=reconf_k if args.path == "reconf" else 0)
     pr_seconds[args.path] = time.perf_counter() - t0
     results, facts = run_plan(pr, args.modes.split(","), args.path)
     n_slices, batch, costs = facts["n_slices"], facts["batch"], facts["costs"]
@@ -257,10 +260,10 @@ def main():
     variant = None
     if args.path_variant and args.path == "greedy":
         t0 = time.perf_counter()
-        prv = P.prepare(w, reconf_k=8)
+        prv = P.prepare(w, reconf_k=reconf_k)
         pr_seconds["reconf"] = time.perf_counter() - t0
         vres, vf = run_plan(prv, args.path_variant.split(","), "reconf")
-        variant = {"path": "randomised greedy + subtree reconfiguration (k=8)",
+        variant = {"path": f"randomised greedy + subtree reconfiguration (k={reconf_k})",
                    "plan_seconds": round(vf["plan_seconds"], 3),
                    "sliced_indices": vf["n_sliced"], "log2_C_BS": round(vf["costs"].log2_sliced, 4),
                    "overhead": round(vf["costs"].overhead, 5), "macs_per_slice": vf["macs_slice"],
