@@ -406,12 +406,15 @@ ltn_status ltn_permute(const void* d_in, void* d_out, int32_t rank, const int32_
  * kind 0 = generic VALU kernel (tk threads per output), 1 = complex64 MFMA
  * GEMM, 2 = split-precision MFMA GEMM, 3 = narrow-step kernel (k + n <= 10,
  * n <= 6: A tile in LDS, B broadcast from LDS, outputs staged in address
- * order); cfg = tile configuration of that kind (-1 for the generic
- * kernel); swap = operands exchanged (rows come from B). Requires a bound
- * plan. */
+ * order), 4 = split-sum kernel for steps with few outputs (m <= 3, n <= 3:
+ * the sum over k is cut into chunks reduced by separate blocks, FP32
+ * partials added in FP64 in chunk order); cfg = tile configuration of that
+ * kind (-1 for the generic kernel); swap = operands exchanged (rows come
+ * from B). Requires a bound plan. */
 /* Force the kernel of one step in one mode (same encoding as
  * ltn_step_kernel; tk in {1, 8, 64} for kind 0). Errors: LTN_E_INVALID if
- * the kernel does not fit the step (tile too large, narrow limits) or a
+ * the kernel does not fit the step (tile too large, narrow or split-sum
+ * limits) or a
  * split kind is asked for in complex64 mode; LTN_E_STATE if unbound. The
  * plan's captured graphs are dropped. */
 ltn_status ltn_set_step_kernel(ltn_plan* plan, int32_t step, int32_t mode, int32_t kind,

@@ -37,6 +37,7 @@ SOURCES = [
     ("k_permute.hip", "hip"),
     ("k_narrow.hip", "hip"),
     ("k_fused.hip", "hip"),
+    ("k_skinny.hip", "hip"),
 ]
 
 

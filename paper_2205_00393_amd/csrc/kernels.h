@@ -127,6 +127,26 @@ struct NarrowDesc {
 bool narrow_fits(int m, int k, int n);
 void launch_narrow(const NarrowDesc& d, hipStream_t st);
 
+// Steps with few outputs and a long sum (m, n <= 3): C[merge(m, n)] =
+// sum_k A[m 2^k + k] B[n 2^k + k] with the sum split into chunks of
+// 2^kc_bits; FP32 partial sums per chunk, then an FP64 sum over the chunks.
+struct SkinnyDesc {
+  const float2* A;
+  const float2* B;
+  float2* C;
+  int64_t sA, sB, sC;
+  int32_t m, k, n;
+  uint64_t cmask;      // output bit j from A's next free bit if (cmask >> j) & 1
+  int32_t nb;
+  float2* part;        // scratch: [nb][chunks][2^(m+n)] partial sums
+  uint32_t* scale_c;   // if set: record the output's per-slice max |x|
+};
+bool skinny_fits(int m, int k, int n);
+int skinny_chunk_bits(int k);  // log2 of the chunk length
+// scratch elements (complex64) per slice for a step
+int64_t skinny_part_elems(int m, int k, int n);
+void launch_skinny(const SkinnyDesc& d, hipStream_t st);
+
 // Fused sub-path (secondary slicing): piece (b, sigma) reads the contiguous
 // 2^a elements of T_0 at sigma << a, runs the stages in LDS and writes W_L
 // to T_L at pdep(sigma, sig_out) | pdep(w, w_out).

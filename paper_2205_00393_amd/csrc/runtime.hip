@@ -27,7 +27,7 @@ using namespace ltn;
 
 struct Layout {
   size_t leafdata, gd_fwd, gd_grad, gd_gcot, pl, angles, leafgrad, ids, scales, arena, split, gscr,
-      gscr_c, total;
+      gscr_c, skinny, total;
 };
 
 struct ltn_plan_impl {
@@ -46,7 +46,8 @@ struct ltn_plan_impl {
   bool fuse = true;  // run fused sub-paths in forward passes
   // kernel choice per mode and step: kind 0 = generic (tk threads per
   // output), 1 = complex64 MFMA GEMM, 2 = split MFMA GEMM (cfg, swap),
-  // 3 = narrow-step kernel (swap: rows taken from the B operand)
+  // 3 = narrow-step kernel (swap: rows taken from the B operand), 4 = split
+  // sum over k for steps with few outputs
   struct Choice {
     int kind = 0, cfg = -1, swap = 0, tk = 1;
   };
@@ -102,6 +103,12 @@ Layout layout(const ltn_plan* p, int B, int grad) {
   o = al(o + (size_t)B * so);
   l.gscr_c = o;
   o = al(o + (size_t)B * sc);
+  // partial sums of the few-output steps (largest over the steps that fit)
+  int64_t sk = 0;
+  for (auto& sp : p->steps)
+    if (skinny_fits(sp.m, sp.k, sp.n)) sk = std::max<int64_t>(sk, skinny_part_elems(sp.m, sp.k, sp.n));
+  l.skinny = o;
+  o = al(o + (size_t)B * (size_t)sk * 8);
   l.total = o;
   return l;
 }
@@ -169,6 +176,24 @@ void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena, int mode) {
   const uint64_t cm = sp.c_mask_a, full = (sp.m + sp.n) >= 64 ? ~0ull : ((1ull << (sp.m + sp.n)) - 1);
   const auto& ch = r.choice[mode][s];
   const bool split = mode != LTN_C64;
+  if (ch.kind == 4) {
+    SkinnyDesc d{};
+    d.A = A;
+    d.B = B;
+    d.C = C;
+    d.sA = int64_t(1) << ta.rank;
+    d.sB = int64_t(1) << tb.rank;
+    d.sC = int64_t(1) << tc.rank;
+    d.m = sp.m;
+    d.k = sp.k;
+    d.n = sp.n;
+    d.cmask = cm;
+    d.nb = nb;
+    d.part = reinterpret_cast<float2*>(r.ws + r.lay.skinny);
+    if (mode == LTN_SPLIT_F16) d.scale_c = slot(p, sp.out);
+    launch_skinny(d, r.st);
+    return;
+  }
   if (ch.kind == 3) {
     NarrowDesc d{};
     const bool sw = ch.swap;
@@ -492,6 +517,11 @@ extern "C" ltn_status ltn_bind(ltn_plan* p, void* d_ws, size_t bytes, int32_t gr
               }
             }
           }
+        }
+        // few outputs and a long sum: split the sum over blocks
+        if (ch.kind == 0 && skinny_fits(sp.m, sp.k, sp.n) && sp.k >= 10) {
+          ch.kind = 4;
+          ch.cfg = 0;
         }
         // steps with many output rows and no MFMA tile: the narrow kernel
         if (ch.kind == 0 && sp.m + sp.n >= 12) {
@@ -883,8 +913,9 @@ void drop_graphs(ltn_plan* p) {
 
 // Candidates: every MFMA tile configuration that fits the step in either
 // operand role (split tiles first in the split modes, then complex64 tiles),
-// the narrow-step kernel in either role (k + n <= 10), and the generic
-// kernel with 1, 8 or 64 threads per output on small steps.
+// the narrow-step kernel in either role (k + n <= 10), the split-sum kernel
+// (m, n <= 3), and the generic kernel with 1, 8 or 64 threads per output on
+// small steps.
 // Cache entries: [kind * 1000 + cfg, swap] for MFMA kinds, [-tk, 0] for the
 // generic kernel.
 extern "C" ltn_status ltn_autotune(ltn_plan* p, int32_t mode, const char* cache_path) {
@@ -946,8 +977,14 @@ extern "C" ltn_status ltn_autotune(ltn_plan* p, int32_t mode, const char* cache_
             ch.swap = sw;
             cands.push_back(ch);
           }
+        if (skinny_fits(sp.m, sp.k, sp.n)) {
+          Choice ch;
+          ch.kind = 4;
+          ch.cfg = 0;
+          cands.push_back(ch);
+        }
         // the generic kernel only competes on small steps (or when no tile fits)
-        if (cands.empty() || sp.m + sp.k + sp.n <= 22)
+        if (cands.empty() || (cands.size() == 1 && cands[0].kind == 4) || sp.m + sp.k + sp.n <= 22)
           for (int tk : {1, 8, 64})
             if (tk == 1 || (1 << sp.k) >= tk) {
               Choice ch;
@@ -1041,6 +1078,10 @@ extern "C" ltn_status ltn_set_step_kernel(ltn_plan* p, int32_t step, int32_t mod
       c.kind = 3;
       c.cfg = 0;
       c.swap = swap ? 1 : 0;
+    } else if (kind == 4) {
+      require(skinny_fits(sp.m, sp.k, sp.n), "the split-sum kernel needs m <= 3 and n <= 3");
+      c.kind = 4;
+      c.cfg = 0;
     } else {
       require(false, "unknown kernel kind");
     }

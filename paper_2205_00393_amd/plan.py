@@ -164,11 +164,12 @@ class Plan:
     def set_step_kernel(self, k: int, mode: str, kind: int, cfg: int = 0, swap: int = 0,
                         tk: int = 1) -> None:
         """Force the kernel of step k in a mode (kind 0 generic with tk, 1
-        complex64 MFMA, 2 split MFMA, 3 narrow)."""
+        complex64 MFMA, 2 split MFMA, 3 narrow, 4 split sum for m, n <= 3)."""
         L.check(L.lib().ltn_set_step_kernel(self._h, k, L.MODES[mode], kind, cfg, swap, tk))
 
     def step_kernel(self, k: int, mode: str = "c64"):
-        """(kind, cfg, swap, tk): kind 0 generic, 1 complex64 MFMA, 2 split MFMA."""
+        """(kind, cfg, swap, tk): kind 0 generic, 1 complex64 MFMA, 2 split MFMA,
+        3 narrow, 4 split sum."""
         kind, cfg, sw, tk = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         L.check(L.lib().ltn_step_kernel(self._h, k, L.MODES[mode], C.byref(kind), C.byref(cfg),
                                         C.byref(sw), C.byref(tk)))

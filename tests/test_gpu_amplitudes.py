@@ -184,20 +184,22 @@ TOL_SPLIT = 5e-4
 
 
 @pytest.mark.parametrize("mode", ["c64", "split_f16", "split_bf16"])
-def test_rqc30_reconfigured_path(torch, mode):
+@pytest.mark.parametrize("reconf_k", [8, 10])
+def test_rqc30_reconfigured_path(torch, mode, reconf_k):
     """The 30-qubit workload on the path improved by subtree reconfiguration
     (different tree, same amplitudes): all slices, autotuned, against the
-    stored oracle amplitudes."""
+    stored oracle amplitudes. Window 8 leaves 4 sliced indices; window 10
+    finds a tree that needs none (one slice, its root step a split sum)."""
     import paper_2205_00393_amd as P
     path = os.path.join(GOLDEN, "rqc30_amplitudes.npy")
     if not os.path.exists(path):
         pytest.skip("golden rqc30 amplitudes not generated")
     ref = np.load(path)
     w = make_workload("rqc30")
-    pr = P.prepare(w, reconf_k=8)
+    pr = P.prepare(w, reconf_k=reconf_k)
     plan = pr.plan()
     n = 1 << len(pr.sliced)
-    banner(f"rqc30 reconfigured path |S|={len(pr.sliced)} {mode}")
+    banner(f"rqc30 reconfigured path (k={reconf_k}) |S|={len(pr.sliced)} {mode}")
     plan.bind(batch=n)
     plan.autotune(mode)
     out = plan.execute_range(0, n, mode=mode)

@@ -19,6 +19,8 @@ VARIANTS = {
     "generic_tk64": [(0, -1, 0, 64)],
     "mfma_c64": [(1, c, s, 1) for s in (0, 1) for c in range(16)],
     "mfma_split": [(2, c, s, 1) for s in (0, 1) for c in range(16)],
+    # split sum over k for few-output steps (m, n <= 3)
+    "split_sum": [(4, 0, 0, 1)],
     # split tiles staged by global_load_lds (configurations 10-15)
     "mfma_split_dma": [(2, c, s, 1) for s in (0, 1) for c in range(10, 16)],
 }
@@ -151,3 +153,27 @@ def test_split_producer_writes_split_layout(torch, prepared_fat, mode):
     err = rel_l2(out.cpu().numpy(), ref)
     banner(f"{mode} with direct split operands: rel err {err:.3e}")
     assert err < 5e-4
+
+
+@pytest.mark.parametrize("m,k,n", [(3, 20, 3), (0, 16, 2), (2, 13, 0), (1, 5, 3), (3, 0, 3), (2, 11, 2)])
+def test_split_sum_single_step(torch, m, k, n):
+    """The split-sum kernel alone on one-step networks: C = A B with 2^m x
+    2^k and 2^k x 2^n complex64 operands (k = 0 is an outer product; k = 20
+    runs 512 chunks), in every mode, against the exact product."""
+    import paper_2205_00393_amd as P
+    rng = np.random.default_rng(1000 + 100 * m + 10 * n + k)
+    M, K, N = 1 << m, 1 << k, 1 << n
+    a = (rng.standard_normal((M, K)) + 1j * rng.standard_normal((M, K))).astype(np.complex64)
+    b = (rng.standard_normal((K, N)) + 1j * rng.standard_normal((K, N))).astype(np.complex64)
+    mi, ki, ni = list(range(m)), list(range(m, m + k)), list(range(m + k, m + k + n))
+    net = P.Network.from_arrays([mi + ki, ki + ni], [a, b], mi + ni, m + k + n)
+    plan = P.Plan(net, [(0, 1)], [])
+    plan.bind(batch=1, budget_bytes=1 << 30)
+    exact = (a.astype(np.complex128) @ b.astype(np.complex128)).reshape(-1)
+    for mode in ("c64", "split_f16", "split_bf16"):
+        plan.set_step_kernel(0, mode, 4, 0, 0, 1)
+        out = plan.execute([0], mode=mode)
+        torch.cuda.synchronize()
+        err = rel_l2(out.cpu().numpy(), exact)
+        banner(f"split sum ({m},{k},{n}) {mode}: rel err {err:.2e}")
+        assert err < 1e-5
