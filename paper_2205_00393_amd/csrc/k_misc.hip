@@ -229,8 +229,9 @@ __device__ __forceinline__ uint64_t madd(uint64_t a, uint64_t d, uint64_t mask) 
   return ((a | ~mask) + d) & mask;
 }
 
+// blk / nblk: this block's index and the number of blocks working on d
 template <int TK>
-__global__ __launch_bounds__(256) void k_generic(GenericDesc d) {
+__device__ __forceinline__ void generic_body(const GenericDesc& d, uint64_t blk, uint64_t nblk) {
   const int per_block = 256 / TK;
   const int lane = threadIdx.x % TK;
   const uint64_t n_out = 1ull << (d.xb + d.yb);
@@ -242,8 +243,7 @@ __global__ __launch_bounds__(256) void k_generic(GenericDesc d) {
   // atomic when the slice changes and once after the loop)
   uint64_t bcur = ~0ull;
   float vcur = 0.f;
-  for (uint64_t g = (uint64_t)blockIdx.x * per_block + threadIdx.x / TK; g < total;
-       g += (uint64_t)gridDim.x * per_block) {
+  for (uint64_t g = blk * per_block + threadIdx.x / TK; g < total; g += nblk * per_block) {
     uint64_t b = g >> (d.xb + d.yb);
     uint64_t o = g & (n_out - 1);
     // o enumerates the output in linear order: recover x, y from its bits
@@ -300,6 +300,20 @@ __global__ __launch_bounds__(256) void k_generic(GenericDesc d) {
       raise_max(d.scale_out + bcur, vcur);
     }
   }
+}
+
+template <int TK>
+__global__ __launch_bounds__(256) void k_generic(GenericDesc d) {
+  generic_body<TK>(d, blockIdx.x, gridDim.x);
+}
+
+// Several independent generic contractions in one launch: grid row y runs
+// descriptor y (from device memory) for nb slices.
+template <int TK>
+__global__ __launch_bounds__(256) void k_generic_multi(const GenericDesc* descs, int nb) {
+  GenericDesc d = descs[blockIdx.y];
+  d.nb = nb;
+  generic_body<TK>(d, blockIdx.x, gridDim.x);
 }
 
 int grid_for(uint64_t items, int per_block) {
@@ -381,6 +395,19 @@ void launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
   if (n16 == 0) return;
   hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(n16, 256) < 4096 ? grid_for(n16, 256) : 4096),
                      dim3(256), 0, st, (uint4*)p, n16);
+}
+
+void launch_generic_multi(const GenericDesc* d_descs, int n, uint64_t max_outs, int nb, int tk,
+                          hipStream_t st) {
+  if (n <= 0) return;
+  const uint64_t outs = max_outs * (uint64_t)nb;
+  const int per_block = tk == 1 ? 256 : (tk == 8 ? 32 : 4);
+  const dim3 grid((unsigned)grid_for(outs, per_block), (unsigned)n);
+  switch (tk) {
+    case 1: hipLaunchKernelGGL(k_generic_multi<1>, grid, dim3(256), 0, st, d_descs, nb); break;
+    case 8: hipLaunchKernelGGL(k_generic_multi<8>, grid, dim3(256), 0, st, d_descs, nb); break;
+    default: hipLaunchKernelGGL(k_generic_multi<64>, grid, dim3(256), 0, st, d_descs, nb); break;
+  }
 }
 
 void launch_generic(const GenericDesc& d, int tk, hipStream_t st) {

@@ -76,6 +76,10 @@ void launch_u3_adjoint(const ParamLeaf* d_pl, int n, const double* angles, const
                        double* angle_grad, hipStream_t st);
 void launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 void launch_generic(const GenericDesc& d, int tk, hipStream_t st);
+// n independent descriptors (device array) in one launch over nb slices;
+// max_outs: largest 2^(xb + yb) among them
+void launch_generic_multi(const GenericDesc* d_descs, int n, uint64_t max_outs, int nb, int tk,
+                          hipStream_t st);
 
 // C[merge(m, n)] = sum_k A[m 2^k + k] B[n 2^k + k] on FP32 MFMA; the output
 // bit j comes from A's next free bit if (cmask >> j) & 1, else from B's.

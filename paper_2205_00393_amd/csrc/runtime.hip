@@ -27,7 +27,7 @@ using namespace ltn;
 
 struct Layout {
   size_t leafdata, gd_fwd, gd_grad, gd_gcot, pl, angles, leafgrad, ids, scales, arena, split, gscr,
-      gscr_c, skinny, total;
+      gscr_c, skinny, gdesc, total;
 };
 
 struct ltn_plan_impl {
@@ -58,6 +58,16 @@ struct ltn_plan_impl {
   // gradients, full batches: recomputed forward and adjoint sweep
   hipGraphExec_t ggraph[2] = {nullptr, nullptr};
   hipGraph_t ggraph_src[2] = {nullptr, nullptr};
+  // gradient launch sequence: runs of independent generic contractions of
+  // consecutive steps share one launch (descriptors in the workspace)
+  struct GradItem {
+    int what = 0;  // 0: forward step, 1: generic run, 2: large adjoint step
+    int step = -1, off = 0, count = 0, tk = 1;
+    uint64_t max_outs = 0;
+  };
+  bool gseq_valid = false;
+  std::vector<GenericDesc> gseq_descs;
+  std::vector<GradItem> gseq_fwd, gseq_bwd;
   std::vector<uint64_t> host_ids;
 };
 
@@ -109,6 +119,8 @@ Layout layout(const ltn_plan* p, int B, int grad) {
     if (skinny_fits(sp.m, sp.k, sp.n)) sk = std::max<int64_t>(sk, skinny_part_elems(sp.m, sp.k, sp.n));
   l.skinny = o;
   o = al(o + (size_t)B * (size_t)sk * 8);
+  l.gdesc = o;  // gradient runs: at most one descriptor per step forward, two backward
+  if (grad) o = al(o + 3 * p->steps.size() * sizeof(GenericDesc));
   l.total = o;
   return l;
 }
@@ -164,6 +176,32 @@ bool split_direct(ltn_plan* p, int t, int mode, bool gradarena) {
   if (fused(T.producer) || fused(T.consumer)) return false;
   const int kp = r.choice[mode][T.producer].kind, kc = r.choice[mode][T.consumer].kind;
   return (kp == 1 || kp == 2) && kc == 2;
+}
+
+// The generic kernel's descriptor for forward step s.
+GenericDesc step_generic_desc(ltn_plan* p, int s, int nb, bool gradarena, int mode) {
+  const StepPlan& sp = p->steps[s];
+  const TensorPlan &ta = p->tensors[sp.a], &tb = p->tensors[sp.b], &tc = p->tensors[sp.out];
+  const uint64_t cm = sp.c_mask_a, full = (sp.m + sp.n) >= 64 ? ~0ull : ((1ull << (sp.m + sp.n)) - 1);
+  GenericDesc g{};
+  g.P = arena_ptr(p, gradarena ? ta.goff : ta.off);
+  g.Q = arena_ptr(p, gradarena ? tb.goff : tb.off);
+  g.out = arena_ptr(p, gradarena ? tc.goff : tc.off);
+  g.sP = int64_t(1) << ta.rank;
+  g.sQ = int64_t(1) << tb.rank;
+  g.sO = int64_t(1) << tc.rank;
+  g.xb = sp.m;
+  g.yb = sp.n;
+  g.zb = sp.k;
+  g.px = ((1ull << sp.m) - 1) << sp.k;
+  g.pz = (1ull << sp.k) - 1;
+  g.qy = ((1ull << sp.n) - 1) << sp.k;
+  g.qz = (1ull << sp.k) - 1;
+  g.ox = cm;
+  g.oy = ~cm & full;
+  g.nb = nb;
+  if (mode == LTN_SPLIT_F16) g.scale_out = slot(p, sp.out);
+  return g;
 }
 
 void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena, int mode) {
@@ -262,24 +300,7 @@ void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena, int mode) {
     }
     launch_cgemm(d, ch.kind == 2 ? mode : LTN_C64, r.st);
   } else {
-    GenericDesc g{};
-    g.P = A;
-    g.Q = B;
-    g.out = C;
-    g.sP = int64_t(1) << ta.rank;
-    g.sQ = int64_t(1) << tb.rank;
-    g.sO = int64_t(1) << tc.rank;
-    g.xb = sp.m;
-    g.yb = sp.n;
-    g.zb = sp.k;
-    g.px = ((1ull << sp.m) - 1) << sp.k;
-    g.pz = (1ull << sp.k) - 1;
-    g.qy = ((1ull << sp.n) - 1) << sp.k;
-    g.qz = (1ull << sp.k) - 1;
-    g.ox = cm;
-    g.oy = ~cm & full;
-    g.nb = nb;
-    if (mode == LTN_SPLIT_F16) g.scale_out = slot(p, sp.out);
+    GenericDesc g = step_generic_desc(p, s, nb, gradarena, mode);
     launch_generic(g, ch.tk, r.st);
   }
 }
@@ -331,6 +352,16 @@ void enqueue_forward(ltn_plan* p, int nb, bool gradarena, int mode) {
   launch_gather(gd, (int)p->leaves.size(), r.max_leaf_elems,
                 reinterpret_cast<const float2*>(r.ws + r.lay.leafdata), arena_ptr(p, 0),
                 reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids), nb, scales, r.B, r.st);
+  if (gradarena && r.gseq_valid) {
+    const GenericDesc* dd = reinterpret_cast<const GenericDesc*>(r.ws + r.lay.gdesc);
+    for (const auto& it : r.gseq_fwd) {
+      if (it.what == 0)
+        enqueue_step(p, it.step, nb, true, mode);
+      else
+        launch_generic_multi(dd + it.off, it.count, it.max_outs, nb, it.tk, r.st);
+    }
+    return;
+  }
   for (int s = 0; s < (int)p->steps.size(); ++s) {
     const int g = p->step_group[s];
     if (g >= 0 && r.fuse && !gradarena) {
@@ -693,66 +724,67 @@ static const float2* enqueue_perm(ltn_plan* p, const float2* in, float2* out,
   return out;
 }
 
-// Adjoint sweep of one batch (steps in reverse order), then the leaf
-// cotangents accumulated into the per-leaf FP64 sums. Every pointer is in
-// the bound workspace, so a full batch can run from a captured graph.
-static void enqueue_backward(ltn_plan* p, int nb) {
+// Adjoint of a small step for one operand (which 0: A, 1: B) on the
+// generic kernel: the output cotangent times the other operand, conjugated,
+// summed over the other operand's free bits; operands read in place.
+static GenericDesc adj_generic_desc(ltn_plan* p, int s, int which, int nb, int* tk) {
+  const StepPlan& sp = p->steps[s];
+  const TensorPlan &ta = p->tensors[sp.a], &tb = p->tensors[sp.b], &tc = p->tensors[sp.out];
+  const uint64_t cm = sp.c_mask_a, full = (1ull << (sp.m + sp.n)) - 1;
+  GenericDesc g{};
+  g.P = arena_ptr(p, tc.gcot);
+  g.sP = int64_t(1) << tc.rank;
+  g.yb = sp.k;
+  g.qy = (1ull << sp.k) - 1;
+  g.oy = (1ull << sp.k) - 1;
+  g.conjQ = 1;
+  g.nb = nb;
+  if (which == 0) {
+    g.Q = arena_ptr(p, tb.goff);
+    g.out = arena_ptr(p, ta.gcot);
+    g.sQ = int64_t(1) << tb.rank;
+    g.sO = int64_t(1) << ta.rank;
+    g.xb = sp.m;
+    g.zb = sp.n;
+    g.px = cm;
+    g.pz = ~cm & full;
+    g.qz = ((1ull << sp.n) - 1) << sp.k;
+    g.ox = ((1ull << sp.m) - 1) << sp.k;
+    *tk = default_tk(sp.n, (1ull << (sp.m + sp.k)) * (uint64_t)nb);
+  } else {
+    g.Q = arena_ptr(p, ta.goff);
+    g.out = arena_ptr(p, tb.gcot);
+    g.sQ = int64_t(1) << ta.rank;
+    g.sO = int64_t(1) << tb.rank;
+    g.xb = sp.n;
+    g.zb = sp.m;
+    g.px = ~cm & full;
+    g.pz = cm;
+    g.qz = ((1ull << sp.m) - 1) << sp.k;
+    g.ox = ((1ull << sp.n) - 1) << sp.k;
+    *tk = default_tk(sp.m, (1ull << (sp.n + sp.k)) * (uint64_t)nb);
+  }
+  return g;
+}
+
+// Adjoint of step s (operand cotangents from the output's cotangent).
+static void enqueue_adjoint_step(ltn_plan* p, int s, int nb) {
   auto& r = *p->rt;
-  double* lg = reinterpret_cast<double*>(r.ws + r.lay.leafgrad);
-  const GatherDesc* gcot = reinterpret_cast<const GatherDesc*>(r.ws + r.lay.gd_gcot);
-  const uint64_t* dids = reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids);
-  for (int s = (int)p->steps.size() - 1; s >= 0; --s) {
-    const StepPlan& sp = p->steps[s];
-    if (!r.needs_grad[sp.out]) continue;
-    const TensorPlan &ta = p->tensors[sp.a], &tb = p->tensors[sp.b], &tc = p->tensors[sp.out];
-    const uint64_t cm = sp.c_mask_a;
+  const StepPlan& sp = p->steps[s];
+  if (!r.needs_grad[sp.out]) return;
+  const TensorPlan &ta = p->tensors[sp.a], &tb = p->tensors[sp.b], &tc = p->tensors[sp.out];
+  const uint64_t cm = sp.c_mask_a;
+  {
     // small steps: one generic kernel per operand, reading the operands
     // in place (strided) and conjugating the second one
     if (sp.m + sp.n + sp.k <= 16) {
-      const uint64_t full = (1ull << (sp.m + sp.n)) - 1;
-      if (r.needs_grad[sp.a]) {
-        GenericDesc g{};
-        g.P = arena_ptr(p, tc.gcot);
-        g.Q = arena_ptr(p, tb.goff);
-        g.out = arena_ptr(p, ta.gcot);
-        g.sP = int64_t(1) << tc.rank;
-        g.sQ = int64_t(1) << tb.rank;
-        g.sO = int64_t(1) << ta.rank;
-        g.xb = sp.m;
-        g.yb = sp.k;
-        g.zb = sp.n;
-        g.px = cm;
-        g.pz = ~cm & full;
-        g.qy = (1ull << sp.k) - 1;
-        g.qz = ((1ull << sp.n) - 1) << sp.k;
-        g.ox = ((1ull << sp.m) - 1) << sp.k;
-        g.oy = (1ull << sp.k) - 1;
-        g.conjQ = 1;
-        g.nb = nb;
-        launch_generic(g, default_tk(sp.n, (1ull << (sp.m + sp.k)) * (uint64_t)nb), r.st);
-      }
-      if (r.needs_grad[sp.b]) {
-        GenericDesc g{};
-        g.P = arena_ptr(p, tc.gcot);
-        g.Q = arena_ptr(p, ta.goff);
-        g.out = arena_ptr(p, tb.gcot);
-        g.sP = int64_t(1) << tc.rank;
-        g.sQ = int64_t(1) << ta.rank;
-        g.sO = int64_t(1) << tb.rank;
-        g.xb = sp.n;
-        g.yb = sp.k;
-        g.zb = sp.m;
-        g.px = ~cm & full;
-        g.pz = cm;
-        g.qy = (1ull << sp.k) - 1;
-        g.qz = ((1ull << sp.m) - 1) << sp.k;
-        g.ox = ((1ull << sp.n) - 1) << sp.k;
-        g.oy = (1ull << sp.k) - 1;
-        g.conjQ = 1;
-        g.nb = nb;
-        launch_generic(g, default_tk(sp.m, (1ull << (sp.n + sp.k)) * (uint64_t)nb), r.st);
-      }
-      continue;
+      for (int which = 0; which < 2; ++which)
+        if (r.needs_grad[which ? sp.b : sp.a]) {
+          int tk = 1;
+          GenericDesc g = adj_generic_desc(p, s, which, nb, &tk);
+          launch_generic(g, tk, r.st);
+        }
+      return;
     }
     // adjoint products in the forward form: the output cotangent
     // and the other operand are permuted so that the summed bits are
@@ -788,8 +820,111 @@ static void enqueue_backward(ltn_plan* p, int nb) {
                  int64_t(1) << tb.rank, sp.n, sp.m, sp.k, ((1ull << sp.n) - 1) << sp.k, nb);
     }
   }
+}
+
+// Adjoint sweep of one batch (steps in reverse order), then the leaf
+// cotangents accumulated into the per-leaf FP64 sums. Every pointer is in
+// the bound workspace, so a full batch can run from a captured graph.
+static void enqueue_backward(ltn_plan* p, int nb) {
+  auto& r = *p->rt;
+  double* lg = reinterpret_cast<double*>(r.ws + r.lay.leafgrad);
+  const GatherDesc* gcot = reinterpret_cast<const GatherDesc*>(r.ws + r.lay.gd_gcot);
+  const uint64_t* dids = reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids);
+  if (r.gseq_valid) {
+    const GenericDesc* dd = reinterpret_cast<const GenericDesc*>(r.ws + r.lay.gdesc);
+    for (const auto& it : r.gseq_bwd) {
+      if (it.what == 1)
+        launch_generic_multi(dd + it.off, it.count, it.max_outs, nb, it.tk, r.st);
+      else
+        enqueue_adjoint_step(p, it.step, nb);
+    }
+  } else {
+    for (int s = (int)p->steps.size() - 1; s >= 0; --s) enqueue_adjoint_step(p, s, nb);
+  }
   launch_leaf_cot_accumulate(reinterpret_cast<const ParamLeaf*>(r.ws + r.lay.pl), r.n_pl, gcot,
                              arena_ptr(p, 0), dids, nb, lg, r.st);
+}
+
+// Gradient launch sequence. The gradient arena gives every tensor and every
+// cotangent a place of its own, so consecutive generic contractions can
+// share one launch as long as none of them reads what another one writes:
+// forward, a step that consumes a tensor the run produces starts a new run;
+// backward (reverse order), a step whose output cotangent the run writes
+// does. Other kernels keep their place between the runs. The descriptors
+// (for the bound batch size; the launch passes the actual one) are copied
+// to the workspace here, outside any capture.
+static void build_grad_seq(ltn_plan* p) {
+  auto& r = *p->rt;
+  using Item = ltn_plan_impl::GradItem;
+  r.gseq_descs.clear();
+  r.gseq_fwd.clear();
+  r.gseq_bwd.clear();
+  std::vector<std::pair<GenericDesc, int>> run;
+  std::vector<char> written(p->tensors.size(), 0);
+  std::vector<int> wlist;
+  auto flush = [&](std::vector<Item>& seq) {
+    for (int tk : {1, 8, 64}) {
+      Item it;
+      it.what = 1;
+      it.tk = tk;
+      it.off = (int)r.gseq_descs.size();
+      for (auto& e : run)
+        if (e.second == tk) {
+          r.gseq_descs.push_back(e.first);
+          it.max_outs = std::max<uint64_t>(it.max_outs, 1ull << (e.first.xb + e.first.yb));
+        }
+      it.count = (int)r.gseq_descs.size() - it.off;
+      if (it.count) seq.push_back(it);
+    }
+    run.clear();
+    for (int t : wlist) written[t] = 0;
+    wlist.clear();
+  };
+  auto single = [&](std::vector<Item>& seq, int what, int s) {
+    flush(seq);
+    Item it;
+    it.what = what;
+    it.step = s;
+    seq.push_back(it);
+  };
+  for (int s = 0; s < (int)p->steps.size(); ++s) {
+    const StepPlan& sp = p->steps[s];
+    const auto& ch = r.choice[LTN_C64][s];
+    if (ch.kind != 0) {
+      single(r.gseq_fwd, 0, s);
+      continue;
+    }
+    if (written[sp.a] || written[sp.b]) flush(r.gseq_fwd);
+    run.push_back({step_generic_desc(p, s, r.B, true, LTN_C64), ch.tk});
+    written[sp.out] = 1;
+    wlist.push_back(sp.out);
+  }
+  flush(r.gseq_fwd);
+  for (int s = (int)p->steps.size() - 1; s >= 0; --s) {
+    const StepPlan& sp = p->steps[s];
+    if (!r.needs_grad[sp.out]) continue;
+    if (sp.m + sp.n + sp.k > 16) {
+      single(r.gseq_bwd, 2, s);
+      continue;
+    }
+    if (written[sp.out]) flush(r.gseq_bwd);
+    for (int which = 0; which < 2; ++which) {
+      const int t = which ? sp.b : sp.a;
+      if (!r.needs_grad[t]) continue;
+      int tk = 1;
+      run.push_back({adj_generic_desc(p, s, which, r.B, &tk), tk});
+      written[t] = 1;
+      wlist.push_back(t);
+    }
+  }
+  flush(r.gseq_bwd);
+  require(r.gseq_descs.size() <= 3 * p->steps.size(), "gradient descriptor area too small");
+  if (!r.gseq_descs.empty())
+    HIPCHECK(hipMemcpyAsync(r.ws + r.lay.gdesc, r.gseq_descs.data(), r.gseq_descs.size() * sizeof(GenericDesc),
+                            hipMemcpyHostToDevice, r.st));
+  // the host array may be rebuilt by a later call: let the copy finish
+  HIPCHECK(hipStreamSynchronize(r.st));
+  r.gseq_valid = true;
 }
 
 extern "C" ltn_status ltn_execute_grad(ltn_plan* p, const uint64_t* ids, uint64_t n, int32_t mode,
@@ -805,6 +940,7 @@ extern "C" ltn_status ltn_execute_grad(ltn_plan* p, const uint64_t* ids, uint64_
     if (ns < 64)
       for (uint64_t i = 0; i < n; ++i) require(ids[i] < (1ull << ns), "slice id is not below 2^|S|");
     double* lg = reinterpret_cast<double*>(r.ws + r.lay.leafgrad);
+    if (!r.gseq_valid) build_grad_seq(p);
     launch_fill_zero(lg, al((size_t)r.n_pl * 64), r.st);
     const uint64_t* dids = reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids);
     // full batches run the recomputed forward and the adjoint sweep from two
@@ -907,6 +1043,7 @@ void drop_graphs(ltn_plan* p) {
     r.ggraph[m] = nullptr;
     r.ggraph_src[m] = nullptr;
   }
+  r.gseq_valid = false;  // kernel choices may have changed
 }
 
 }  // namespace
