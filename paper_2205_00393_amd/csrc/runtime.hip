@@ -27,7 +27,7 @@ using namespace ltn;
 
 struct Layout {
   size_t leafdata, gd_fwd, gd_grad, gd_gcot, pl, angles, leafgrad, ids, scales, arena, split, gscr,
-      gscr_c, skinny, gdesc, total;
+      gscr_c, skinny, gdesc, fdesc, total;
 };
 
 struct ltn_plan_impl {
@@ -68,6 +68,10 @@ struct ltn_plan_impl {
   bool gseq_valid = false;
   std::vector<GenericDesc> gseq_descs;
   std::vector<GradItem> gseq_fwd, gseq_bwd;
+  // forward launch sequence per mode (what 0: step, 1: generic run, 3: fused group)
+  bool fseq_valid[3] = {false, false, false};
+  std::vector<GenericDesc> fseq_descs[3];
+  std::vector<GradItem> fseq[3];
   std::vector<uint64_t> host_ids;
 };
 
@@ -121,6 +125,8 @@ Layout layout(const ltn_plan* p, int B, int grad) {
   o = al(o + (size_t)B * (size_t)sk * 8);
   l.gdesc = o;  // gradient runs: at most one descriptor per step forward, two backward
   if (grad) o = al(o + 3 * p->steps.size() * sizeof(GenericDesc));
+  l.fdesc = o;  // forward runs: one descriptor per step and mode
+  o = al(o + 3 * std::max<size_t>(1, p->steps.size()) * sizeof(GenericDesc));
   l.total = o;
   return l;
 }
@@ -362,6 +368,19 @@ void enqueue_forward(ltn_plan* p, int nb, bool gradarena, int mode) {
     }
     return;
   }
+  if (!gradarena && r.fseq_valid[mode]) {
+    const GenericDesc* dd =
+        reinterpret_cast<const GenericDesc*>(r.ws + r.lay.fdesc) + (size_t)mode * p->steps.size();
+    for (const auto& it : r.fseq[mode]) {
+      if (it.what == 0)
+        enqueue_step(p, it.step, nb, false, mode);
+      else if (it.what == 3)
+        enqueue_group(p, it.step, nb, mode);
+      else
+        launch_generic_multi(dd + it.off, it.count, it.max_outs, nb, it.tk, r.st);
+    }
+    return;
+  }
   for (int s = 0; s < (int)p->steps.size(); ++s) {
     const int g = p->step_group[s];
     if (g >= 0 && r.fuse && !gradarena) {
@@ -370,6 +389,87 @@ void enqueue_forward(ltn_plan* p, int nb, bool gradarena, int mode) {
     }
     enqueue_step(p, s, nb, gradarena, mode);
   }
+}
+
+// Forward launch sequence of a mode: consecutive generic steps share one
+// launch unless one of them reads, or writes over, memory another one
+// writes or reads (the arena reuses memory once a tensor is dead, so the
+// test is on per-slice byte ranges, not tensor ids). Fused sub-paths keep
+// their launch at their last step. Descriptors (for the bound batch size)
+// are copied to the workspace here, outside any capture.
+void build_fwd_seq(ltn_plan* p, int mode) {
+  auto& r = *p->rt;
+  using Item = ltn_plan_impl::GradItem;
+  auto& seq = r.fseq[mode];
+  auto& descs = r.fseq_descs[mode];
+  seq.clear();
+  descs.clear();
+  struct Range {
+    uint64_t lo, hi;
+  };
+  auto range = [&](int t) { return Range{p->tensors[t].off, p->tensors[t].off + p->tensors[t].bytes()}; };
+  auto overlap = [](Range a, Range b) { return a.lo < b.hi && b.lo < a.hi; };
+  std::vector<std::pair<GenericDesc, int>> run;
+  std::vector<Range> reads, writes;
+  auto flush = [&]() {
+    for (int tk : {1, 8, 64}) {
+      Item it;
+      it.what = 1;
+      it.tk = tk;
+      it.off = (int)descs.size();
+      for (auto& e : run)
+        if (e.second == tk) {
+          descs.push_back(e.first);
+          it.max_outs = std::max<uint64_t>(it.max_outs, 1ull << (e.first.xb + e.first.yb));
+        }
+      it.count = (int)descs.size() - it.off;
+      if (it.count) seq.push_back(it);
+    }
+    run.clear();
+    reads.clear();
+    writes.clear();
+  };
+  for (int s = 0; s < (int)p->steps.size(); ++s) {
+    const StepPlan& sp = p->steps[s];
+    const int g = p->step_group[s];
+    if (g >= 0 && r.fuse) {
+      if (s == p->groups[g].st.back().step) {
+        flush();
+        Item it;
+        it.what = 3;
+        it.step = g;
+        seq.push_back(it);
+      }
+      continue;
+    }
+    const auto& ch = r.choice[mode][s];
+    if (ch.kind != 0) {
+      flush();
+      Item it;
+      it.what = 0;
+      it.step = s;
+      seq.push_back(it);
+      continue;
+    }
+    const Range ra = range(sp.a), rb = range(sp.b), rc = range(sp.out);
+    bool clash = false;
+    for (auto& w : writes) clash = clash || overlap(w, ra) || overlap(w, rb) || overlap(w, rc);
+    for (auto& q : reads) clash = clash || overlap(q, rc);
+    if (clash) flush();
+    run.push_back({step_generic_desc(p, s, r.B, false, mode), ch.tk});
+    reads.push_back(ra);
+    reads.push_back(rb);
+    writes.push_back(rc);
+  }
+  flush();
+  require(descs.size() <= p->steps.size(), "forward descriptor area too small");
+  if (!descs.empty()) {
+    char* dst = r.ws + r.lay.fdesc + (size_t)mode * p->steps.size() * sizeof(GenericDesc);
+    HIPCHECK(hipMemcpyAsync(dst, descs.data(), descs.size() * sizeof(GenericDesc), hipMemcpyHostToDevice, r.st));
+    // the host array may be rebuilt by a later call: let the copy finish
+    HIPCHECK(hipStreamSynchronize(r.st));
+  }
+  r.fseq_valid[mode] = true;
 }
 
 void enqueue_reduce(ltn_plan* p, int nb, bool gradarena, double* out) {
@@ -427,6 +527,7 @@ void launch_captured(ltn_plan* p, hipGraphExec_t& exec, hipGraph_t& src, F&& enq
 
 void run_batch(ltn_plan* p, int nb, int mode, double* out) {
   auto& r = *p->rt;
+  if (!r.fseq_valid[mode]) build_fwd_seq(p, mode);
   if (nb == r.B) {
     launch_captured(p, r.graph[mode], r.graph_src[mode], [&] { enqueue_forward(p, nb, false, mode); });
   } else {
@@ -1043,7 +1144,8 @@ void drop_graphs(ltn_plan* p) {
     r.ggraph[m] = nullptr;
     r.ggraph_src[m] = nullptr;
   }
-  r.gseq_valid = false;  // kernel choices may have changed
+  r.gseq_valid = false;  // kernel choices or fusion may have changed
+  for (int m = 0; m < 3; ++m) r.fseq_valid[m] = false;
 }
 
 }  // namespace
