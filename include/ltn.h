@@ -353,8 +353,10 @@ ltn_status ltn_bind(ltn_plan* plan, void* d_workspace, size_t bytes, int32_t gra
  * ADD the result into d_out (complex128, 2^n_open entries, device).
  * Slices are summed in FP64, in batches of the bound batch size; within a
  * batch in ascending position, batches in call order. Asynchronous on the
- * bound stream. Errors: LTN_E_STATE (unbound), LTN_E_INVALID (bad id /
- * mode). */
+ * bound stream, except that the first call in a mode after ltn_bind, a
+ * kernel choice or a fusion change synchronises it once (the launch
+ * descriptors of that mode are uploaded and a graph is captured). Errors:
+ * LTN_E_STATE (unbound), LTN_E_INVALID (bad id / mode). */
 ltn_status ltn_execute(ltn_plan* plan, const uint64_t* slice_ids, uint64_t n, int32_t mode,
                        void* d_out);
 /* Same for the slice ids begin .. end-1. */
@@ -372,7 +374,10 @@ ltn_status ltn_set_params(ltn_plan* plan, const double* d_angles);
  * the loss gradient with respect to the output vector (complex128,
  * 2^n_open entries, PyTorch convention dL/dRe + i dL/dIm). Adds the
  * forward result into d_out (may be NULL) and dL/dangle into d_angle_grad
- * (float64 [n_params]). Requires a plan bound with grad != 0. */
+ * (float64 [n_params]). Requires a plan bound with grad != 0. Asynchronous
+ * on the bound stream, except that the first call after ltn_bind or a
+ * kernel choice change synchronises it once (launch descriptors uploaded,
+ * graphs captured). */
 ltn_status ltn_execute_grad(ltn_plan* plan, const uint64_t* slice_ids, uint64_t n, int32_t mode,
                             const void* d_cotangent, void* d_out, double* d_angle_grad);
 
