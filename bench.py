@@ -257,7 +257,7 @@ def main():
     macs_slice, flops_step = facts["macs_slice"], facts["flops_step"]
 
     # the same workload on a better path: greedy trials improved by subtree
-    # reconfiguration (and, for the 53-qubit case, a refined slicing set)
+    # reconfiguration
     variant = None
     if args.path_variant and args.path == "greedy":
         t0 = time.perf_counter()

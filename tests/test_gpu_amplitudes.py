@@ -209,6 +209,35 @@ def test_rqc30_reconfigured_path(torch, mode, reconf_k):
     assert err < (TOL_C64 if mode == "c64" else TOL_SPLIT)
 
 
+@pytest.mark.parametrize("mode", ["c64", "split_bf16"])
+def test_rqc30_refined_slicing(torch, mode):
+    """A slicing set from the refiner (Algorithms 2-4, seeds 0 and 1) on the
+    reconfigured 30-qubit path: a different set of sliced indices with no
+    larger cost, contracted over all its slices against the stored oracle
+    amplitudes."""
+    import paper_2205_00393_amd as P
+    path = os.path.join(GOLDEN, "rqc30_amplitudes.npy")
+    if not os.path.exists(path):
+        pytest.skip("golden rqc30 amplitudes not generated")
+    ref = np.load(path)
+    w = make_workload("rqc30")
+    base = P.prepare(w, reconf_k=8)
+    pr = P.prepare(w, reconf_k=8, refine_seeds=2)
+    assert sorted(pr.sliced) != sorted(base.sliced)
+    c0 = P.tree_costs(base.net, base.path, base.sliced).sliced
+    c1 = P.tree_costs(pr.net, pr.path, pr.sliced).sliced
+    assert c1 <= c0
+    plan = pr.plan()
+    n = 1 << len(pr.sliced)
+    banner(f"rqc30 refined slicing {sorted(pr.sliced)} (was {sorted(base.sliced)}) {mode}")
+    plan.bind(batch=n)
+    out = plan.execute_range(0, n, mode=mode)
+    torch.cuda.synchronize()
+    err = rel_l2(out.cpu().numpy(), ref)
+    banner(f"rqc30 refined slicing {mode} rel err {err:.3e}")
+    assert err < (TOL_C64 if mode == "c64" else TOL_SPLIT)
+
+
 @pytest.mark.parametrize("mode", ["split_f16", "split_bf16"])
 @pytest.mark.parametrize("fat", [1, 0])
 def test_reduced_split_precision(torch, mode, fat):
