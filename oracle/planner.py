@@ -22,22 +22,29 @@ greedy); ties go to the lexicographically smallest (lower id, higher id);
 when no pair shares an index, the two lowest ids are joined by an outer
 product. SSA ids: leaves 0..L-1, the k-th contraction creates L+k.
 
-Tie-breaks of Algorithm 1 (the paper does not give them):
-* ``sT`` = M[0] if M[0].dim < M[-1].dim else M[-1] (ties go to M[-1]);
-* ``T.dim`` = rank after removing the indices already in S;
-* "longest lifetime" = most tensors of the current M holding the index,
-  then most tensors of the whole tree, then the smaller index id;
-* off-stem tensors still above t afterwards (post-order, SSA order): add
-  their unsliced index with the longest whole-tree lifetime (then smaller
-  id) until they fit.
+Readings of the slice finder (Sec. 4.2, Algorithm 1; the paper does not
+give tie-breaks):
+* ranks are taken after removing the indices already in S; the stem
+  tensors at or below t are set aside before each choice, so the two ends
+  compared are those of the over-cap part (the stem always starts at a
+  leaf; whenever that leaf fits, this is the order of the paper's loop);
+* of the two ends the one of smaller rank is fixed next, the root-side one
+  on a tie;
+* "longest lifetime" = the index's stem lifetime (an interval of stem
+  positions) covers the most over-cap stem tensors, then the most tensors
+  of the whole tree hold it, then the smaller index id;
+* off-stem tensors still above t afterwards (SSA order): add their unsliced
+  index with the longest whole-tree lifetime (then smaller id) until they
+  fit.
 
 Slice refiner (Sec. 4.3, Algorithms 2-4), readings where the paper is
 silent:
 * lifetime of an index = every tree tensor holding it (leaves included);
   ``dim`` = rank after removing the current S; critical tensors of a sliced
   index = tensors of its lifetime whose dim equals t (Algorithm 3);
-* candidates = the indices common to all its critical tensors (Algorithm 4),
-  minus the current S, in ascending id;
+* candidates = the unsliced indices whose lifetime contains all of its
+  critical tensors (Sec. 4.3; the same set as Algorithm 4's intersection of
+  the critical tensors' index sets), in ascending id;
 * a sliced index whose lifetime holds no critical tensor is dropped from S
   (it reduces no tensor to the cap, Sec. 4.3), which lowers C(B,S);
 * candidate moves act on the chosen slot in turn: each proposal replaces
@@ -233,12 +240,49 @@ class Tree:
         return out[::-1]
 
 
-def slice_finder(tree: Tree, t: int, pre: Sequence[int] = (),
-                 stem: Optional[List[int]] = None) -> List[int]:
-    """Algorithm 1 on the stem, then the off-stem fix-up, starting from the
-    already-sliced indices ``pre``. Returns S = pre + the indices in the
-    order they were added (bit j of a slice id is the value of S[j]).
-    t < 0 means no cap."""
+def stem_intervals(tree: Tree, stem: Sequence[int]) -> Dict[int, Tuple[int, int]]:
+    """Lifetime of every index on the stem, as a closed interval of stem
+    positions. By the Linearity theorem (supplement) the tensors holding an
+    index lie on one path of the tree, and a path meets the stem (another
+    path) in one contiguous stretch, so an interval describes it exactly."""
+    iv: Dict[int, Tuple[int, int]] = {}
+    for p, v in enumerate(stem):
+        for x in tree.sets[v]:
+            lo, _ = iv.get(x, (p, p))
+            iv[x] = (lo, p)
+    return iv
+
+
+def pick_end(over: Sequence[int], rank) -> int:
+    """Which end of the over-cap part of the stem is fixed next (Sec. 4.2:
+    the search starts from both ends of the stem): the end tensor of smaller
+    rank, the root-side end when the two are equal. ``over`` holds stem
+    positions, leaf side first; ``rank(p)`` is the rank after slicing."""
+    return over[0] if rank(over[0]) < rank(over[-1]) else over[-1]
+
+
+def lifetime_order(cands: Sequence[int], span: Dict[int, int], whole: Dict[int, int]) -> List[int]:
+    """Indices ordered best first for slicing (Sec. 4.2: an index whose
+    lifetime covers more of the remaining over-cap stem is preferred):
+    longer span over the over-cap stem tensors, then more tree tensors
+    holding the index, then the smaller id."""
+    return sorted(cands, key=lambda x: (-span[x], -whole[x], x))
+
+
+def slice_finder(tree: Tree, t: int, pre: Sequence[int] = ()) -> List[int]:
+    """Lifetime-based slice finder (Sec. 4.2, Algorithm 1) on the stem,
+    then the off-stem fix-up, starting from the already-sliced indices
+    ``pre``. Returns S = pre + the indices in the order they were added
+    (bit j of a slice id is the value of S[j]). t < 0 means no cap.
+
+    The stem tensors whose rank after slicing exceeds t form the part of
+    the stem still to fix. Each round takes one end of that part (the M_1
+    of the paper; the rest is M_2), slices as many of its unsliced indices
+    as it exceeds t by, choosing those whose stem lifetime covers most of
+    the over-cap tensors, and drops the tensors that now fit. Tensors off
+    the stem that still exceed t (the paper says most branches fit, not
+    all) are fixed afterwards in id order, each by its unsliced index held
+    by the most tree tensors (then the smaller id)."""
     S: List[int] = list(pre)
     if t < 0:
         return S
@@ -248,37 +292,28 @@ def slice_finder(tree: Tree, t: int, pre: Sequence[int] = (),
         ps = set(pre)
         tree = Tree([[x for x in tree.sets[v] if x not in ps] for v in range(tree.L)], tree.path)
     inS = set()
-    M = list(tree.stem() if stem is None else stem)
-    whole = {}
+
+    def rank(v):
+        return len(tree.sets[v] - inS)
+
+    stem = tree.stem()
+    iv = stem_intervals(tree, stem)
+    whole: Dict[int, int] = {}
     for s in tree.sets:
         for x in s:
             whole[x] = whole.get(x, 0) + 1
-
-    def dim(v):
-        return len(tree.sets[v] - inS)
-
-    def lifetimes(M):
-        lf = {}
-        for v in M:
-            for x in tree.sets[v]:
-                lf[x] = lf.get(x, 0) + 1
-        return lf
-
-    M = [v for v in M]
-    lf = lifetimes(M)
-    while M:
-        sT = M[0] if dim(M[0]) < dim(M[-1]) else M[-1]
-        need = dim(sT) - t
-        if need > 0:
-            cand = sorted((x for x in tree.sets[sT] if x not in inS),
-                          key=lambda x: (-lf[x], -whole[x], x))
-            for x in cand[:need]:
-                S.append(x)
-                inS.add(x)
-        M = [v for v in M if dim(v) > t]
-        lf = lifetimes(M)
+    over = [p for p, v in enumerate(stem) if rank(v) > t]
+    while over:
+        p = pick_end(over, lambda q: rank(stem[q]))
+        v = stem[p]
+        cands = [x for x in tree.sets[v] if x not in inS]
+        span = {x: sum(1 for q in over if iv[x][0] <= q <= iv[x][1]) for x in cands}
+        for x in lifetime_order(cands, span, whole)[:rank(v) - t]:
+            S.append(x)
+            inS.add(x)
+        over = [q for q in over if rank(stem[q]) > t]
     for v in range(len(tree.sets)):
-        while dim(v) > t:
+        while rank(v) > t:
             x = min((y for y in tree.sets[v] if y not in inS), key=lambda y: (-whole[y], y))
             S.append(x)
             inS.add(x)
@@ -313,19 +348,21 @@ def path_search(leaf_indices, t: int, pre: Sequence[int] = (), alphas=(1.0,), ta
 
 
 def critical_tensors(tree: Tree, S: Sequence[int], index: int, t: int) -> List[int]:
-    """Algorithm 3: the tensors in the lifetime of ``index`` whose rank after
-    slicing S equals the target t."""
+    """The critical tensors of a sliced index (Sec. 4.3; Algorithm 3): the
+    tensors of its lifetime whose rank after slicing S is exactly t."""
     Sset = set(S)
     return [v for v in tree.lifetime(index) if len(tree.sets[v] - Sset) == t]
 
 
 def candidate_indices(tree: Tree, crit: Sequence[int], S: Sequence[int]) -> List[int]:
-    """Algorithm 4: indices held by every critical tensor, excluding the
-    sliced ones; ascending id."""
-    cand = set(tree.sets[crit[0]])
-    for v in crit:
-        cand &= tree.sets[v]
-    return sorted(cand - set(S))
+    """Replacements for a sliced index with critical tensors ``crit``
+    (Sec. 4.3; Algorithm 4): the unsliced indices whose lifetime contains
+    every critical tensor, ascending id. Slicing one of them instead keeps
+    every critical tensor at t, so the cap still holds."""
+    need = set(crit)
+    Sset = set(S)
+    everywhere = set().union(*(tree.sets[v] for v in crit))
+    return sorted(x for x in everywhere if x not in Sset and need <= set(tree.lifetime(x)))
 
 
 def fits(tree: Tree, S: Sequence[int], t: int) -> bool:

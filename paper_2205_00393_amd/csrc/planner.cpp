@@ -194,6 +194,15 @@ std::vector<int32_t> Tree::stem() const {
   return out;
 }
 
+// Lifetime-based slice finder (Sec. 4.2, Algorithm 1). The lifetime of an
+// index on the stem is one interval of stem positions (Linearity theorem:
+// the tensors holding an index form one path of the tree, which meets the
+// stem in one stretch). The over-cap stem tensors are fixed from the ends
+// inwards: the end of smaller rank (root side on a tie) gets as many of its
+// unsliced indices sliced as it exceeds t by, those whose interval covers
+// the most over-cap tensors first (then the most tree tensors holding the
+// index, then the smaller id). Off-stem tensors still above t are fixed
+// afterwards in id order by their index held by the most tree tensors.
 std::vector<int32_t> slice_finder(const std::vector<IdSet>& leaves, const int32_t* path, int t,
                                   const std::vector<int32_t>& pre) {
   std::vector<int32_t> S(pre.begin(), pre.end());
@@ -208,39 +217,49 @@ std::vector<int32_t> slice_finder(const std::vector<IdSet>& leaves, const int32_
   for (auto& s : tree.sets)
     for (int32_t x : s) whole[x]++;
   IdSet inS;  // sorted, the indices added here
-  auto dim = [&](int32_t v) { return (int)set_minus(tree.sets[v], inS).size(); };
+  auto rank = [&](int32_t v) { return (int)set_minus(tree.sets[v], inS).size(); };
   auto add = [&](int32_t x) {
     S.push_back(x);
     inS.insert(std::lower_bound(inS.begin(), inS.end(), x), x);
   };
-  std::vector<int32_t> M = tree.stem();
-  auto lifetimes = [&]() {
-    std::unordered_map<int32_t, int> lf;
-    for (int32_t v : M)
-      for (int32_t x : tree.sets[v]) lf[x]++;
-    return lf;
-  };
-  auto lf = lifetimes();
-  while (!M.empty()) {
-    int32_t sT = dim(M.front()) < dim(M.back()) ? M.front() : M.back();
-    int need = dim(sT) - t;
-    if (need > 0) {
-      IdSet cand = set_minus(tree.sets[sT], inS);
-      std::sort(cand.begin(), cand.end(), [&](int32_t x, int32_t y) {
-        if (lf[x] != lf[y]) return lf[x] > lf[y];
-        if (whole[x] != whole[y]) return whole[x] > whole[y];
-        return x < y;
-      });
-      for (int i = 0; i < need; ++i) add(cand[i]);
+  const std::vector<int32_t> stem = tree.stem();
+  std::unordered_map<int32_t, std::pair<int, int>> iv;  // index -> [first, last] stem position
+  for (int p = 0; p < (int)stem.size(); ++p)
+    for (int32_t x : tree.sets[stem[p]]) {
+      auto it = iv.find(x);
+      if (it == iv.end()) iv.emplace(x, std::make_pair(p, p));
+      else it->second.second = p;
     }
-    std::vector<int32_t> keep;
-    for (int32_t v : M)
-      if (dim(v) > t) keep.push_back(v);
-    M.swap(keep);
-    lf = lifetimes();
+  std::vector<int> over;  // stem positions still above t, leaf side first
+  auto trim = [&]() {
+    std::vector<int> keep;
+    for (int p : over)
+      if (rank(stem[p]) > t) keep.push_back(p);
+    over.swap(keep);
+  };
+  for (int p = 0; p < (int)stem.size(); ++p) over.push_back(p);
+  trim();
+  while (!over.empty()) {
+    const int p = rank(stem[over.front()]) < rank(stem[over.back()]) ? over.front() : over.back();
+    const int32_t v = stem[p];
+    IdSet cand = set_minus(tree.sets[v], inS);
+    std::unordered_map<int32_t, int> span;
+    for (int32_t x : cand) {
+      auto [lo, hi] = iv[x];
+      span[x] = (int)(std::upper_bound(over.begin(), over.end(), hi) -
+                      std::lower_bound(over.begin(), over.end(), lo));
+    }
+    std::sort(cand.begin(), cand.end(), [&](int32_t x, int32_t y) {
+      if (span[x] != span[y]) return span[x] > span[y];
+      if (whole[x] != whole[y]) return whole[x] > whole[y];
+      return x < y;
+    });
+    const int need = rank(v) - t;
+    for (int i = 0; i < need; ++i) add(cand[i]);
+    trim();
   }
   for (int32_t v = 0; v < n; ++v) {
-    while (dim(v) > t) {
+    while (rank(v) > t) {
       IdSet cand = set_minus(tree.sets[v], inS);
       int32_t best = cand[0];
       for (int32_t x : cand)
@@ -326,6 +345,10 @@ std::vector<int32_t> slice_refine(const Tree& tree, int t, const std::vector<int
   require(p.iters_per_temp >= 1, "iters_per_temp must be >= 1");
   require(p.alpha > 0.0 && p.alpha < 1.0, "alpha must be in (0, 1)");
   require(p.tf > 0.0 && p.t0 > 0.0, "temperatures must be positive");
+  // lifetime of every index: the tree tensors holding it, ascending id
+  std::vector<std::vector<int32_t>> life(max_id + 1);
+  for (int32_t v = 0; v < (int32_t)tree.sets.size(); ++v)
+    for (int32_t x : tree.sets[v]) life[x].push_back(v);
   RefineStats stats;
   std::vector<int32_t> cur = S0;
   SlicedCost sc(tree);
@@ -342,10 +365,10 @@ std::vector<int32_t> slice_refine(const Tree& tree, int t, const std::vector<int
       const double u = keyed_uniform(p.seed, (uint64_t)it, 0, 0);
       const int slot = p.n_fixed + std::min((int)(u * free), free - 1);
       const int32_t idx = cur[slot];
-      // Algorithm 3: critical tensors in the lifetime of idx
+      // critical tensors of idx (Algorithm 3): its lifetime at rank t
       std::vector<int32_t> crit;
-      for (int32_t v = 0; v < (int32_t)tree.sets.size(); ++v)
-        if (set_has(tree.sets[v], idx) && dim_after(tree.sets[v], inS) == t) crit.push_back(v);
+      for (int32_t v : life[idx])
+        if (dim_after(tree.sets[v], inS) == t) crit.push_back(v);
       if (crit.empty()) {
         inS[idx] = 0;
         cur.erase(cur.begin() + slot);
@@ -353,12 +376,17 @@ std::vector<int32_t> slice_refine(const Tree& tree, int t, const std::vector<int
         cur_c = sc.variant(-1, -1);
         ++stats.dropped;
       } else {
-        // Algorithm 4: indices held by every critical tensor, not sliced
-        IdSet cand = tree.sets[crit[0]];
-        for (int32_t v : crit) cand = set_and(cand, tree.sets[v]);
+        // replacements (Algorithm 4): unsliced indices whose lifetime
+        // contains every critical tensor; each holds crit[0], so only its
+        // indices need checking
         IdSet c2;
-        for (int32_t x : cand)
-          if (!inS[x]) c2.push_back(x);
+        for (int32_t x : tree.sets[crit[0]]) {
+          if (inS[x]) continue;
+          bool all = true;
+          for (int32_t v : crit)
+            if (!std::binary_search(life[x].begin(), life[x].end(), v)) { all = false; break; }
+          if (all) c2.push_back(x);
+        }
         for (int32_t c : c2) {
           const int32_t occupant = cur[slot];
           BigSum new_c = sc.variant(occupant, c);

@@ -1,6 +1,8 @@
 """Pins of the oracle planner: Eq. (3) worked example, Eq. (1)/(2)/(4),
-the halving/doubling rule, lifetime linearity, Algorithm 1 against brute
-force, and the no-overhead case of lifetimes spanning a whole sub-path."""
+the halving/doubling rule, lifetime linearity, Algorithm 1 on hand-worked
+stems and against brute force, and the no-overhead case of lifetimes
+spanning a whole sub-path."""
+import collections
 import itertools
 import json
 import os
@@ -180,6 +182,87 @@ def test_slice_finder_vs_brute_force(seed):
         assert tree.space(S) <= 2 ** t                 # memory constraint (Sec. 4.1)
         assert len(S) >= _min_slicing(tree, n, t)      # never below the optimum
         assert pl.slice_finder(tree, t) == S           # deterministic
+
+
+def _alg1_cases():
+    return json.load(open(os.path.join(GOLDEN, "alg1_stems.json")))["cases"]
+
+
+@pytest.mark.parametrize("case", _alg1_cases(), ids=lambda c: c["name"])
+def test_slice_finder_hand_worked_stems(case):
+    """Sec. 4.2, Algorithm 1 on three chains whose slicing sets were worked
+    out by hand (the steps are in tests/golden/alg1_stems.json). In the
+    first the leaf-side end of the over-cap stem has the smaller rank and
+    is fixed first, in the second the root-side end, in the third the two
+    ends tie and the root side goes first. Each one's set depends on which
+    end is taken and on preferring the index whose lifetime covers the most
+    over-cap stem tensors; each reaches the brute-force minimum."""
+    tree = pl.Tree(case["leaves"], [tuple(p) for p in case["path"]])
+    assert tree.stem() == [0, 6, 7, 8, 9, 10]
+    for v, ix in case["node_sets"].items():
+        assert tree.sets[int(v)] == frozenset(ix)
+    n = 1 + max(x for leaf in case["leaves"] for x in leaf)
+    S = pl.slice_finder(tree, case["t"])
+    assert S == case["S"]
+    assert tree.space(S) <= 2 ** case["t"]
+    assert _min_slicing(tree, n, case["t"]) == case["brute_force_min"] == len(S)
+
+
+def _gap_histogram():
+    """|S| of the slice finder minus the smallest |S| meeting the cap, over
+    200 random networks (8 tensors, 13 closed and 2 open indices) on their
+    greedy trees, at the three caps just below the largest tensor."""
+    hist = collections.Counter()
+    for seed in range(200):
+        idx, n, _ = random_network(seed, 8, 13, 2)
+        tree = pl.Tree(idx, pl.greedy_path(idx))
+        W = max(len(s) for s in tree.sets)
+        for t in range(max(1, W - 3), W):
+            hist[len(pl.slice_finder(tree, t)) - _min_slicing(tree, n, t)] += 1
+    return hist
+
+
+def test_slice_finder_gap_to_brute_force():
+    """The paper claims a slicing set "as small as possible", not the
+    smallest (Sec. 4.2). Measured here: the set is minimal in 386 of 600
+    cases, one index above in 188, two above in 26 (never below, never
+    more). The assertions keep that quality; an index ranking that prefers
+    short lifetimes reaches the minimum in only 26 % of the cases (see
+    test_slice_finder_pins_catch_misreadings)."""
+    hist = _gap_histogram()
+    total = sum(hist.values())
+    print("gap histogram", sorted(hist.items()))
+    assert min(hist) >= 0
+    assert hist[0] / total >= 0.6
+    assert sum(g * c for g, c in hist.items()) / total <= 0.45
+
+
+def test_slice_finder_pins_catch_misreadings(monkeypatch):
+    """Three misreadings of Algorithm 1, planted in the oracle, each change
+    the slicing set of at least one hand-worked stem: taking the larger
+    end first, taking the leaf-side end on a tie, and preferring indices
+    with short lifetimes (which also fails the brute-force gap bound)."""
+    cases = _alg1_cases()
+
+    def sets():
+        return [pl.slice_finder(pl.Tree(c["leaves"], [tuple(p) for p in c["path"]]), c["t"])
+                for c in cases]
+
+    want = [c["S"] for c in cases]
+    assert sets() == want
+    with monkeypatch.context() as m:
+        m.setattr(pl, "pick_end", lambda over, rank: over[-1] if rank(over[0]) < rank(over[-1]) else over[0])
+        assert sets() != want
+    with monkeypatch.context() as m:
+        m.setattr(pl, "pick_end", lambda over, rank: over[0] if rank(over[0]) <= rank(over[-1]) else over[-1])
+        got = sets()
+        assert got != want and got[:2] == want[:2]
+    with monkeypatch.context() as m:
+        m.setattr(pl, "lifetime_order",
+                  lambda cands, span, whole: sorted(cands, key=lambda x: (span[x], -whole[x], x)))
+        assert all(g != w for g, w in zip(sets(), want))
+        hist = _gap_histogram()
+        assert hist[0] / sum(hist.values()) < 0.3
 
 
 def test_slice_finder_prefix_and_no_cap():

@@ -70,6 +70,23 @@ def test_random_networks_greedy_costs_stem(seed):
             assert P.slice_finder(cnet, po, t) == opl.slice_finder(tree, t)
 
 
+def test_slice_finder_hand_worked_stems():
+    """The library's Algorithm 1 on the hand-worked chains of
+    tests/golden/alg1_stems.json (Sec. 4.2)."""
+    import json
+    import os
+    fix = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "alg1_stems.json")))
+    for case in fix["cases"]:
+        idx = case["leaves"]
+        n = 1 + max(x for leaf in idx for x in leaf)
+        opens = [x for x in range(n) if sum(x in leaf for leaf in idx) == 1]
+        data = [np.ones([2] * len(ix), dtype=np.complex64) for ix in idx]
+        cnet = P.Network.from_arrays(idx, data, opens, n)
+        path = [tuple(p) for p in case["path"]]
+        assert P.tree_stem(cnet, path) == [0, 6, 7, 8, 9, 10]
+        assert P.slice_finder(cnet, path, case["t"]) == case["S"]
+
+
 @pytest.mark.parametrize("name,t", [("rqc30", 26), ("rqc30", 22), ("rqc12", 6), ("rqc53", 30)])
 def test_slice_finder_bit_exact(name, t):
     w, onet, cnet = _both(name)
