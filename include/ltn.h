@@ -168,14 +168,31 @@ ltn_status ltn_tree_costs(const ltn_network* net, const int32_t* path, const int
 ltn_status ltn_tree_stem(const ltn_network* net, const int32_t* path, int32_t* stem_out,
                          int32_t cap, int32_t* len);
 
-/* Slice finder (Algorithm 1) on the stem under target rank t, starting
- * from the indices in `pre` (already sliced), followed by a fix-up that
- * slices, for every tree tensor still above t (SSA order), its unsliced
- * index held by the most tree tensors (then the smaller id). Algorithm 1
- * tie-breaks: sT = M[0] if M[0].dim < M[N-1].dim else M[N-1]; "longest
- * lifetime" = most tensors of the current M holding the index, then most
- * tree tensors, then the smaller id. t < 0 means no cap (S = pre).
- * S_out receives pre followed by the added indices (capacity cap). */
+/* Profile of the stem (Sec. 4.2), one row per stem tensor from the leaf to
+ * the root: its node id, its rank, its rank after removing the indices in
+ * S, and log2 of the Eq. (1) cost of the contraction that produces it
+ * (|s_v1 u s_v2 u s_v3|, the node's index set) without and with S (-1 for
+ * the leaf). rows capacity = cap; *len = number of stem tensors. Host only.
+ * Errors: LTN_E_NOMEM if cap is below the stem length. */
+typedef struct ltn_stem_row {
+  int32_t tensor, rank, rank_sliced, node_bits, node_bits_sliced;
+} ltn_stem_row;
+ltn_status ltn_stem_profile(const ltn_network* net, const int32_t* path, const int32_t* S,
+                            int32_t n_sliced, ltn_stem_row* rows, int32_t cap, int32_t* len);
+
+/* Lifetime-based slice finder (Sec. 4.2, Algorithm 1) under target rank t,
+ * starting from the indices in `pre` (already sliced; the tree, its stem
+ * and the lifetimes are taken without them). Ranks are counted after the
+ * current S. The stem tensors above t are fixed from the ends of their
+ * stretch inwards: each round takes the end tensor of smaller rank (the
+ * root-side one on a tie) and slices as many of its unsliced indices as it
+ * exceeds t by, preferring the index whose stem lifetime (an interval of
+ * stem positions) covers the most over-cap stem tensors, then the one held
+ * by the most tree tensors, then the smaller id; tensors that now fit
+ * leave the stretch. A fix-up then slices, for every tree tensor still
+ * above t (SSA order), its unsliced index held by the most tree tensors
+ * (then the smaller id). t < 0 means no cap (S = pre). S_out receives pre
+ * followed by the added indices (capacity cap). */
 ltn_status ltn_slice_finder(const ltn_network* net, const int32_t* path, int32_t t,
                             const int32_t* pre, int32_t n_pre, int32_t* S_out, int32_t cap,
                             int32_t* n_sliced);
@@ -207,7 +224,8 @@ ltn_status ltn_path_search(const ltn_network* net, int32_t t, const int32_t* pre
  * first n_fixed, which never move) with a keyed uniform draw; the critical
  * tensors of its index are the tensors holding it (leaves included) whose
  * rank after S equals t (Algorithm 3); the candidates are the unsliced
- * indices held by all of them (Algorithm 4), tried in ascending id, each
+ * indices whose lifetime contains all of them (Sec. 4.3; the set Algorithm 4
+ * forms by intersecting their index sets), tried in ascending id, each
  * replacing the slot's current occupant: a move that lowers C(B,S) (Eq. 4)
  * is taken, a costlier one with probability exp((C_ori - C_new)/C_ori/T).
  * An index with no critical tensor in its lifetime is dropped from S. T
@@ -238,7 +256,7 @@ ltn_status ltn_slice_refine(const ltn_network* net, const int32_t* path, int32_t
 
 /* Subtree reconfiguration of a contraction tree (a path improvement in the
  * spirit of the local tuning of the tree between slicing steps named in
- * Sec. 2.2). Each sweep visits every contraction node v in SSA order: a
+ * Sec. 2.1.2). Each sweep visits every contraction node v in SSA order: a
  * frontier grows from v by replacing the frontier node with the largest
  * node set (Eq. 1's s_v without the indices in S; ties: smaller id) by its
  * two children, up to k tensors (k in 2..16); the frontier is re-contracted
@@ -255,7 +273,7 @@ ltn_status ltn_tree_reconfigure(const ltn_network* net, const int32_t* path, int
                                 int32_t* path_out);
 
 /* Greedy least-overhead slicer, the strategy the paper attributes to
- * cotengra (Sec. 2.2), for comparison with Algorithm 1: starting from pre,
+ * cotengra (Sec. 2.1.2), for comparison with Algorithm 1: starting from pre,
  * while some tree tensor has rank > t after S, append the unsliced index of
  * such tensors that gives the smallest C(B,S) (Eq. 4); ties: held by the
  * most tensors above t, then the smaller id. S_out capacity = cap. */
@@ -281,11 +299,20 @@ typedef struct ltn_options {
                             0 = no fusion                                   */
 } ltn_options;
 
-/* Compile a plan (host only, no device call): validate the network, the
+/* Compile a plan (host only, no device call) for the problem as Sec. 2.1.1
+ * states it: a network G (every edge of weight 2), a contraction tree B
+ * given by an SSA path, and a slicing set S whose 2^|S| value assignments
+ * are independent subtasks. Validate the network, the
  * SSA path and the slicing set, assign every tensor its layout (unsliced
  * indices sorted by the step that contracts them, earliest = lowest bit;
- * open indices last, in output order), give every step its (m, k, n) bit
- * groups and kernel, and lay tensors out in a per-slice arena by liveness.
+ * open indices last, in output order; since an index shared by the two
+ * operands of a contraction is absent from its result (Lemma 1,
+ * supplement), the summed indices are the lowest bits of both operands and
+ * every step is a GEMM without operand transposition), give every step its
+ * (m, k, n) bit groups and kernel (per slice the steps' multiply-adds sum to
+ * C(B,S) / 2^|S|, Eq. (4)), and lay tensors out in a per-slice arena by
+ * liveness; no tensor exceeds 2^t elements when max_rank = t (the memory
+ * bound of Sec. 4.1).
  * Errors: LTN_E_INVALID (index in more than two leaves, open index not
  * listed, path not an SSA cover, duplicate / unknown sliced id, more than
  * 255 sliced indices, a tensor of rank > 40 after slicing), LTN_E_CAP
@@ -338,19 +365,34 @@ typedef struct ltn_step_info {
 ltn_status ltn_plan_step(const ltn_plan* plan, int32_t step, ltn_step_info* out);
 
 /* Bytes of workspace for `batch` slices per batch (grad != 0: enough for
- * ltn_execute_grad as well). */
+ * ltn_execute_grad as well): leaf data and descriptors, then per slice the
+ * arena of the tensors live at once (each at most 2^t complex64 elements
+ * under the cap t of Sec. 4.1), split-precision operand copies and
+ * split-sum partials. The paper keeps each subtask's tensors in one
+ * process's memory (Sec. 4.1, Sec. 5.2); how a device holds several
+ * slices at once is this library's. Host only. Errors: LTN_E_INVALID for
+ * batch < 1. */
 ltn_status ltn_workspace_size(const ltn_plan* plan, int32_t batch, int32_t grad, size_t* bytes);
 
 /* Bind device memory and a HIP stream (hipStream_t passed as void*; NULL =
- * the default stream). The batch size becomes the largest that fits in
+ * the default stream). The paper has no counterpart (its subtasks run in
+ * separate processes, Sec. 6.1); here several slices of one plan are
+ * resident at once and run in the same launches. d_workspace is caller-
+ * owned device memory of `bytes` bytes, 256-byte aligned, that must stay
+ * allocated until the plan is freed or bound again; the plan keeps its own
+ * captured graphs. The batch size becomes the largest that fits in
  * `bytes` (capped by ltn_options.batch when set); the grad flag must match
  * the one used for ltn_workspace_size. Uploads leaf data (async on the
  * stream). Errors: LTN_E_NOMEM if not even one slice fits. */
 ltn_status ltn_bind(ltn_plan* plan, void* d_workspace, size_t bytes, int32_t grad, void* stream);
 
 /* Contract the listed slices (host array of n ids, each < 2^|S| when
- * |S| < 64) and
- * ADD the result into d_out (complex128, 2^n_open entries, device).
+ * |S| < 64) and ADD the result into d_out (complex128, 2^n_open entries,
+ * caller-owned device memory). Each slice is one of the 2^|S| independent
+ * subtasks of Sec. 2.1.1 and the subtasks' results are accumulated, as
+ * there; the paper's processes meet in one allReduce at the end (Sec.
+ * 6.1), so d_out is only ever added to (the caller zeroes it), which lets
+ * partitioned id lists and ranges be summed.
  * Slices are summed in FP64, in batches of the bound batch size; within a
  * batch in ascending position, batches in call order. Asynchronous on the
  * bound stream, except that the first call in a mode after ltn_bind, a
@@ -359,25 +401,32 @@ ltn_status ltn_bind(ltn_plan* plan, void* d_workspace, size_t bytes, int32_t gra
  * LTN_E_STATE (unbound), LTN_E_INVALID (bad id / mode). */
 ltn_status ltn_execute(ltn_plan* plan, const uint64_t* slice_ids, uint64_t n, int32_t mode,
                        void* d_out);
-/* Same for the slice ids begin .. end-1. */
+/* Same for the slice ids begin .. end-1 (end <= 2^|S| when |S| < 64;
+ * LTN_E_INVALID otherwise or when end < begin). */
 ltn_status ltn_execute_range(ltn_plan* plan, uint64_t begin, uint64_t end, int32_t mode,
                              void* d_out);
 
-/* Rebuild every parameterised (u3) leaf from angles on the device:
+/* The paper has no parameterised gates or gradients; this call and
+ * ltn_execute_grad extend the same sliced contraction to rotation angles.
+ * Rebuild every parameterised (u3) leaf from angles on the device:
  * d_angles is float64 [n_params] laid out [gate][a, b, c] with
  * U = Rz(a) Ry(b) Rz(c). Asynchronous on the bound stream. */
 ltn_status ltn_set_params(ltn_plan* plan, const double* d_angles);
 
 /* Gradient of a real loss with respect to the u3 angles, by an adjoint
- * contraction that recomputes every slice's intermediates (complex64 mode
- * only; other modes return LTN_E_UNSUPPORTED). d_cotangent is
- * the loss gradient with respect to the output vector (complex128,
- * 2^n_open entries, PyTorch convention dL/dRe + i dL/dIm). Adds the
- * forward result into d_out (may be NULL) and dL/dangle into d_angle_grad
- * (float64 [n_params]). Requires a plan bound with grad != 0. Asynchronous
- * on the bound stream, except that the first call after ltn_bind or a
- * kernel choice change synchronises it once (launch descriptors uploaded,
- * graphs captured). */
+ * contraction (not in the paper): each slice stays an independent subtask
+ * (Sec. 2.1.1), its forward contraction is recomputed, each step's two
+ * cotangents are the conjugate products of the output cotangent with the
+ * other operand, and leaf cotangents are summed over slices in FP64 before
+ * the u3 chain rule. d_cotangent is the loss gradient with respect to the
+ * output vector (complex128, 2^n_open entries, PyTorch convention
+ * dL/dRe + i dL/dIm). Adds the forward result into d_out (may be NULL) and
+ * dL/dangle into d_angle_grad (float64 [n_params]); all three are
+ * caller-owned device memory. Asynchronous on the bound stream, except that
+ * the first call after ltn_bind or a kernel choice change synchronises it
+ * once (launch descriptors uploaded, graphs captured). Errors: LTN_E_STATE
+ * if the plan is not bound with grad != 0, LTN_E_INVALID for a bad id or
+ * mode, LTN_E_UNSUPPORTED for the split modes (complex64 only). */
 ltn_status ltn_execute_grad(ltn_plan* plan, const uint64_t* slice_ids, uint64_t n, int32_t mode,
                             const void* d_cotangent, void* d_out, double* d_angle_grad);
 

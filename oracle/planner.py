@@ -59,7 +59,7 @@ silent:
   when keyed_uniform(seed, i, 1, c) < p.
 
 Subtree reconfiguration (a path improvement in the spirit of the local
-tuning of the contraction tree cited in Sec. 2.2; the paper takes its
+tuning of the contraction tree cited in Sec. 2.1.2; the paper takes its
 paths from cotengra instead): for every contraction node v in SSA order,
 grow a frontier from v by repeatedly replacing the frontier node with the
 largest node set (after removing S; ties: smaller id) by its two children,
@@ -72,7 +72,7 @@ part (as a bit mask over the frontier) runs downward. New nodes reuse the
 subtree's ids; after every sweep the tree is written out again as an SSA
 path in post order (left child first).
 
-Greedy-overhead slicer (the strategy attributed to cotengra in Sec. 2.2):
+Greedy-overhead slicer (the strategy attributed to cotengra in Sec. 2.1.2):
 while some tensor is above t, slice the index, among those of tensors above
 t, whose addition gives the smallest C(B,S); ties: held by the most
 tensors above t, then the smaller id.

@@ -5,10 +5,10 @@ execution, both in libltn (C ABI in include/ltn.h); this package marshals
 arguments and lends PyTorch device memory and streams.
 """
 from ._lib import LtnError, lib, MODES
-from .network import (Network, greedy_path, tree_costs, tree_stem, slice_finder, path_search,
-                      slice_refine, slice_greedy_overhead, tree_reconfigure)
+from .network import (Network, greedy_path, tree_costs, tree_stem, stem_profile, slice_finder,
+                      path_search, slice_refine, slice_greedy_overhead, tree_reconfigure)
 from .plan import Plan, Prepared, prepare, permute
 
 __all__ = ["LtnError", "lib", "MODES", "Network", "greedy_path", "tree_costs", "tree_stem",
-           "slice_finder", "path_search", "slice_refine", "slice_greedy_overhead",
+           "stem_profile", "slice_finder", "path_search", "slice_refine", "slice_greedy_overhead",
            "tree_reconfigure", "Plan", "Prepared", "prepare", "permute"]

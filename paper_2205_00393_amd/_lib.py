@@ -37,6 +37,11 @@ class Costs(C.Structure):
                 ("stem_len", C.c_int32)]
 
 
+class StemRow(C.Structure):
+    _fields_ = [("tensor", C.c_int32), ("rank", C.c_int32), ("rank_sliced", C.c_int32),
+                ("node_bits", C.c_int32), ("node_bits_sliced", C.c_int32)]
+
+
 class SearchOpts(C.Structure):
     _fields_ = [("n_alpha", C.c_int32), ("alphas", C.POINTER(C.c_double)),
                 ("n_tau", C.c_int32), ("taus", C.POINTER(C.c_double)),
@@ -89,6 +94,7 @@ SIGNATURES = {
     "ltn_greedy_path": [C.POINTER(Network), I32P, I32, D, D, U64, I32P],
     "ltn_tree_costs": [C.POINTER(Network), I32P, I32P, I32, C.POINTER(Costs)],
     "ltn_tree_stem": [C.POINTER(Network), I32P, I32P, I32, I32P],
+    "ltn_stem_profile": [C.POINTER(Network), I32P, I32P, I32, C.POINTER(StemRow), I32, I32P],
     "ltn_slice_finder": [C.POINTER(Network), I32P, I32, I32P, I32, I32P, I32, I32P],
     "ltn_path_search": [C.POINTER(Network), I32, I32P, I32, C.POINTER(SearchOpts), I32P, I32P, I32,
                         I32P, I32P],

@@ -687,6 +687,35 @@ extern "C" ltn_status ltn_tree_stem(const ltn_network* net, const int32_t* path,
   });
 }
 
+extern "C" ltn_status ltn_stem_profile(const ltn_network* net, const int32_t* path, const int32_t* S,
+                                       int32_t n_sliced, ltn_stem_row* rows, int32_t cap, int32_t* len) {
+  return guarded([&] {
+    Net n = Net::from_abi(net, false);
+    require(path && rows && len, "NULL argument");
+    require(n_sliced == 0 || S != nullptr, "S is NULL");
+    IdSet sl(S, S + n_sliced);
+    std::sort(sl.begin(), sl.end());
+    Tree tree = Tree::build(n.sets, path);
+    auto st = tree.stem();
+    require((int32_t)st.size() <= cap, "rows too small", LTN_E_NOMEM);
+    for (size_t i = 0; i < st.size(); ++i) {
+      const int32_t v = st[i];
+      ltn_stem_row& r = rows[i];
+      r.tensor = v;
+      r.rank = (int32_t)tree.sets[v].size();
+      r.rank_sliced = (int32_t)set_minus(tree.sets[v], sl).size();
+      if (v < tree.L) {
+        r.node_bits = r.node_bits_sliced = -1;
+      } else {
+        const IdSet ns = tree.node_set(v);
+        r.node_bits = (int32_t)ns.size();
+        r.node_bits_sliced = (int32_t)set_minus(ns, sl).size();
+      }
+    }
+    *len = (int32_t)st.size();
+  });
+}
+
 extern "C" ltn_status ltn_slice_finder(const ltn_network* net, const int32_t* path, int32_t t,
                                        const int32_t* pre, int32_t n_pre, int32_t* S_out,
                                        int32_t cap, int32_t* n_sliced) {

@@ -174,6 +174,21 @@ def tree_stem(net: Network, path) -> List[int]:
     return list(out[: n.value])
 
 
+def stem_profile(net: Network, path, S: Sequence[int] = ()) -> List[dict]:
+    """One row per stem tensor, leaf to root (``ltn_stem_profile``): node id,
+    rank, rank after S, and log2 of the Eq. (1) node cost without and with
+    S (None for the leaf)."""
+    cap = 2 * net.n_leaves
+    rows = (L.StemRow * cap)()
+    n = C.c_int32()
+    L.check(L.lib().ltn_stem_profile(C.byref(net.view), _path_array(path), L.i32_array(list(S)), len(S),
+                                     rows, cap, C.byref(n)))
+    return [{"tensor": r.tensor, "rank": r.rank, "rank_sliced": r.rank_sliced,
+             "log2_node_cost": None if r.node_bits < 0 else r.node_bits,
+             "log2_node_cost_sliced": None if r.node_bits_sliced < 0 else r.node_bits_sliced}
+            for r in rows[: n.value]]
+
+
 def slice_finder(net: Network, path, t: int, pre: Sequence[int] = ()) -> List[int]:
     cap = net.n_indices + 1
     out = (C.c_int32 * cap)()

@@ -11,29 +11,10 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 from typing import Dict, List, Sequence
 
-from .network import (Network, slice_finder, slice_greedy_overhead, slice_refine, tree_costs,
-                      tree_stem)
-
-
-def stem_profile(net: Network, path, S: Sequence[int] = ()) -> List[Dict]:
-    """One row per stem tensor, leaf to root: its rank, its rank after S,
-    and log2 of the Eq. (1) node cost of the contraction that makes it."""
-    sets = [frozenset(ix) for ix in net.indices]
-    node = [None] * len(sets)
-    for a, b in path:
-        node.append(sets[a] | sets[b])
-        sets.append(sets[a] ^ sets[b])
-    Sset = set(S)
-    rows = []
-    for v in tree_stem(net, path):
-        s = sets[v]
-        rows.append({"tensor": v, "rank": len(s), "rank_sliced": len(s - Sset),
-                     "log2_node_cost": None if node[v] is None else len(node[v]),
-                     "log2_node_cost_sliced": None if node[v] is None else len(node[v] - Sset)})
-    return rows
+from .network import (Network, slice_finder, slice_greedy_overhead, slice_refine, stem_profile,
+                      tree_costs)
 
 
 def overhead_vs_t(net: Network, path, ts: Sequence[int], pre: Sequence[int] = (),

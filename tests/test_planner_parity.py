@@ -70,6 +70,27 @@ def test_random_networks_greedy_costs_stem(seed):
             assert P.slice_finder(cnet, po, t) == opl.slice_finder(tree, t)
 
 
+@pytest.mark.parametrize("name", ["rqc12", "rqc30", "rqc53"])
+def test_stem_profile_matches_oracle_tree(name):
+    """ltn_stem_profile: ranks and Eq. (1) node sizes along the stem, with
+    and without S, against the oracle's tree."""
+    w, onet, cnet = _both(name)
+    p = opl.greedy_path(onet.indices, 0.5, 0.3, 1)
+    tree = opl.Tree(onet.indices, p)
+    S = opl.slice_finder(tree, w.max_rank if w.max_rank is not None else -1)
+    rows = P.stem_profile(cnet, p, S)
+    assert [r["tensor"] for r in rows] == tree.stem()
+    Ss = set(S)
+    for r in rows:
+        v = r["tensor"]
+        assert r["rank"] == len(tree.sets[v]) and r["rank_sliced"] == len(tree.sets[v] - Ss)
+        if v < tree.L:
+            assert r["log2_node_cost"] is None
+        else:
+            assert r["log2_node_cost"] == len(tree.node_set(v))
+            assert r["log2_node_cost_sliced"] == len(tree.node_set(v) - Ss)
+
+
 def test_slice_finder_hand_worked_stems():
     """The library's Algorithm 1 on the hand-worked chains of
     tests/golden/alg1_stems.json (Sec. 4.2)."""
