@@ -406,6 +406,31 @@ ltn_status ltn_execute(ltn_plan* plan, const uint64_t* slice_ids, uint64_t n, in
 ltn_status ltn_execute_range(ltn_plan* plan, uint64_t begin, uint64_t end, int32_t mode,
                              void* d_out);
 
+/* Size of the library's own device scratch array (one per GPU, held until
+ * the process ends), used by ltn_execute_scratch. */
+#define LTN_SCRATCH_BYTES (64u << 20)
+
+/* ltn_execute for callers that cannot allocate device memory or bind a
+ * workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): contracts the listed slices of a loaded plan
+ * (bound or not; its own binding is left as it is) in the library's
+ * scratch array of LTN_SCRATCH_BYTES on the current device, and ADDS the
+ * result into d_out (complex128, 2^n_open entries, device), with the same
+ * arithmetic and summation order as ltn_execute for the batch size that
+ * fits (as many slices per batch as the scratch holds, at most n). Leaf
+ * data and descriptors are uploaded at every call; batches run eagerly
+ * (no graphs), with the default kernel choices, on `stream` (hipStream_t
+ * as void*; NULL = default stream); the call returns once its uploads are
+ * done and its kernels are enqueued. It allocates nothing: no hipMalloc,
+ * hipFree or allocating library routine. Every call on one GPU uses that
+ * GPU's one scratch array, so calls that overlap on one GPU (other host
+ * threads, other streams) race and must be serialised by the caller; the
+ * array keeps the last call's contents, and whatever must start at zero is
+ * cleared by the call itself. Errors: LTN_E_NOMEM if one slice needs more
+ * than LTN_SCRATCH_BYTES, LTN_E_INVALID (NULL argument, bad id or mode). */
+ltn_status ltn_execute_scratch(ltn_plan* plan, const uint64_t* slice_ids, uint64_t n, int32_t mode,
+                               void* d_out, void* stream);
+
 /* The paper has no parameterised gates or gradients; this call and
  * ltn_execute_grad extend the same sliced contraction to rotation angles.
  * Rebuild every parameterised (u3) leaf from angles on the device:

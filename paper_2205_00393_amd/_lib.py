@@ -109,6 +109,7 @@ SIGNATURES = {
     "ltn_bind": [P, P, C.c_size_t, I32, P],
     "ltn_execute": [P, U64P, U64, I32, P],
     "ltn_execute_range": [P, U64, U64, I32, P],
+    "ltn_execute_scratch": [P, U64P, U64, I32, P, P],
     "ltn_set_params": [P, P],
     "ltn_execute_grad": [P, U64P, U64, I32, P, P, P],
     "ltn_autotune": [P, I32, C.c_char_p],

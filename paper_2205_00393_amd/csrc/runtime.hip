@@ -10,6 +10,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 
 #include "kernels.h"
@@ -572,124 +573,144 @@ extern "C" ltn_status ltn_workspace_size(const ltn_plan* p, int32_t batch, int32
   });
 }
 
+namespace {
+
+// Largest batch whose workspace fits in `bytes`, at most `cap` (0 when not
+// even one slice fits).
+int fit_batch(const ltn_plan* p, size_t bytes, int grad, int cap) {
+  int B = std::min(p->opt.batch > 0 ? p->opt.batch : 4096, 4096);
+  if (p->sliced.size() < 12) B = std::min(B, 1 << p->sliced.size());
+  B = std::max(1, std::min(B, cap));
+  while (B > 1 && layout(p, B, grad).total > bytes) {
+    size_t per = grad ? p->garena : p->arena;
+    size_t fixed = layout(p, 0, grad).total;
+    size_t fit = bytes > fixed ? (bytes - fixed) / (per + 8 + 4 * p->tensors.size() + 512) : 0;
+    B = (int)std::max<size_t>(1, std::min<size_t>(fit, (size_t)B - 1));
+    if (layout(p, B, grad).total <= bytes) break;
+  }
+  return layout(p, B, grad).total <= bytes ? B : 0;
+}
+
+// Fill a device-side state for the workspace d_ws (batch B): gather
+// descriptors, default kernel choices, and the uploads of leaf data and
+// descriptors, synchronised on `st` before returning.
+void bind_state(ltn_plan* p, ltn_plan_impl* r, char* d_ws, size_t bytes, int grad, hipStream_t st,
+                int B) {
+  r->st = st;
+  r->ws = d_ws;
+  r->bytes = bytes;
+  r->grad = grad;
+  r->B = B;
+  r->lay = layout(p, B, grad);
+  // descriptors
+  int gi = 0;
+  for (auto& lp : p->leaves) {
+    require(lp.rank_src <= kMaxLeafRank, "leaf rank above 32 is not supported");
+    GatherDesc g{};
+    g.src_off = lp.src_off;
+    g.rank = lp.rank;
+    g.nsl = (int32_t)lp.sl_bit.size();
+    for (int j = 0; j < lp.rank; ++j) g.src_bit[j] = (int8_t)lp.src_bit[j];
+    for (int j = 0; j < g.nsl; ++j) {
+      g.sl_src_bit[j] = (int8_t)lp.sl_src_bit[j];
+      g.sl_bit[j] = (int8_t)lp.sl_bit[j];
+    }
+    const TensorPlan& t = p->tensors[lp.tensor];
+    g.tensor = lp.tensor;
+    g.dst_off = (int64_t)(t.off * (uint64_t)B / 8);
+    r->gd_fwd.push_back(g);
+    g.dst_off = (int64_t)(t.goff * (uint64_t)B / 8);
+    r->gd_grad.push_back(g);
+    g.dst_off = (int64_t)(t.gcot * (uint64_t)B / 8);
+    r->gd_gcot.push_back(g);
+    r->max_leaf_elems = std::max(r->max_leaf_elems, 1 << lp.rank);
+    if (lp.param >= 0) r->pl.push_back(ParamLeaf{lp.src_off, lp.param, gi});
+    ++gi;
+  }
+  r->n_pl = (int)r->pl.size();
+  for (auto& pr : p->out_sliced) {
+    r->sl_bits.push_back(pr.first);
+    r->out_bits.push_back(pr.second);
+  }
+  require(r->sl_bits.size() <= 32, "more than 32 sliced open indices");
+  // kernel choice per mode and step (refined by ltn_autotune)
+  for (int mode = 0; mode < 3; ++mode)
+    for (auto& sp : p->steps) {
+      ltn_plan_impl::Choice ch;
+      ch.tk = default_tk(sp.k, (1ull << (sp.m + sp.n)) * (uint64_t)B);
+      if (sp.kernel == LTN_K_MFMA) {
+        // MFMA columns follow the output's lowest bits when possible
+        bool nat = (sp.c_mask_a & 1) != 0;
+        for (int kind : {mode == LTN_C64 ? 1 : 2, 1}) {
+          int km = kind == 2 ? mode : LTN_C64;
+          for (bool sw : {nat, !nat}) {
+            int c = sw ? default_cfg(sp.n, sp.k, sp.m, km) : default_cfg(sp.m, sp.k, sp.n, km);
+            if (c >= 0 && ch.kind == 0) {
+              ch.kind = kind;
+              ch.cfg = c;
+              ch.swap = sw;
+            }
+          }
+        }
+      }
+      // few outputs and a long sum: split the sum over blocks
+      if (ch.kind == 0 && skinny_fits(sp.m, sp.k, sp.n) && sp.k >= 10) {
+        ch.kind = 4;
+        ch.cfg = 0;
+      }
+      // steps with many output rows and no MFMA tile: the narrow kernel
+      if (ch.kind == 0 && sp.m + sp.n >= 12) {
+        bool sw = sp.n > sp.m;
+        if (sw ? narrow_fits(sp.n, sp.k, sp.m) : narrow_fits(sp.m, sp.k, sp.n)) {
+          ch.kind = 3;
+          ch.cfg = 0;
+          ch.swap = sw;
+        }
+      }
+      r->choice[mode].push_back(ch);
+    }
+  r->needs_grad.assign(p->tensors.size(), 0);
+  for (size_t v = 0; v < p->tensors.size(); ++v) {
+    if ((int)v < p->L)
+      r->needs_grad[v] = p->leaves[v].param >= 0;
+    else {
+      const StepPlan& sp = p->steps[v - p->L];
+      r->needs_grad[v] = r->needs_grad[sp.left] || r->needs_grad[sp.right];
+    }
+  }
+  // uploads (host vectors live in the plan / impl; synchronised below)
+  HIPCHECK(hipMemcpyAsync(r->ws + r->lay.leafdata, p->leaf_data.data(), (size_t)p->leaf_elems * 8,
+                          hipMemcpyHostToDevice, r->st));
+  HIPCHECK(hipMemcpyAsync(r->ws + r->lay.gd_fwd, r->gd_fwd.data(), r->gd_fwd.size() * sizeof(GatherDesc),
+                          hipMemcpyHostToDevice, r->st));
+  if (grad) {
+    HIPCHECK(hipMemcpyAsync(r->ws + r->lay.gd_grad, r->gd_grad.data(),
+                            r->gd_grad.size() * sizeof(GatherDesc), hipMemcpyHostToDevice, r->st));
+    HIPCHECK(hipMemcpyAsync(r->ws + r->lay.gd_gcot, r->gd_gcot.data(),
+                            r->gd_gcot.size() * sizeof(GatherDesc), hipMemcpyHostToDevice, r->st));
+  }
+  if (r->n_pl)
+    HIPCHECK(hipMemcpyAsync(r->ws + r->lay.pl, r->pl.data(), r->pl.size() * sizeof(ParamLeaf),
+                            hipMemcpyHostToDevice, r->st));
+  HIPCHECK(hipStreamSynchronize(r->st));
+}
+
+}  // namespace
+
 extern "C" ltn_status ltn_bind(ltn_plan* p, void* d_ws, size_t bytes, int32_t grad, void* stream) {
   return guarded([&] {
     require(p != nullptr, "plan is NULL");
     require(d_ws != nullptr, "workspace is NULL");
     require(((uintptr_t)d_ws & 255) == 0, "workspace must be 256-byte aligned");
     // grid.y limit of the gather; no batch larger than the slice count
-    int B = std::min(p->opt.batch > 0 ? p->opt.batch : 4096, 4096);
-    if (p->sliced.size() < 12) B = std::min(B, 1 << p->sliced.size());
-    while (B > 1 && layout(p, B, grad).total > bytes) {
-      size_t per = grad ? p->garena : p->arena;
-      size_t fixed = layout(p, 0, grad).total;
-      size_t fit = bytes > fixed ? (bytes - fixed) / (per + 8 + 4 * p->tensors.size() + 512) : 0;
-      B = (int)std::max<size_t>(1, std::min<size_t>(fit, (size_t)B - 1));
-      if (layout(p, B, grad).total <= bytes) break;
-    }
-    if (layout(p, B, grad).total > bytes)
+    const int B = fit_batch(p, bytes, grad, 4096);
+    if (B == 0)
       fail(LTN_E_NOMEM, "workspace of " + std::to_string(bytes) + " bytes is below the " +
                             std::to_string(layout(p, 1, grad).total) + " needed for one slice");
     runtime_free(p);
     auto r = new ltn_plan_impl();
     p->rt = r;
-    r->st = reinterpret_cast<hipStream_t>(stream);
-    r->ws = reinterpret_cast<char*>(d_ws);
-    r->bytes = bytes;
-    r->grad = grad;
-    r->B = B;
-    r->lay = layout(p, B, grad);
-    // descriptors
-    int gi = 0;
-    for (auto& lp : p->leaves) {
-      require(lp.rank_src <= kMaxLeafRank, "leaf rank above 32 is not supported");
-      GatherDesc g{};
-      g.src_off = lp.src_off;
-      g.rank = lp.rank;
-      g.nsl = (int32_t)lp.sl_bit.size();
-      for (int j = 0; j < lp.rank; ++j) g.src_bit[j] = (int8_t)lp.src_bit[j];
-      for (int j = 0; j < g.nsl; ++j) {
-        g.sl_src_bit[j] = (int8_t)lp.sl_src_bit[j];
-        g.sl_bit[j] = (int8_t)lp.sl_bit[j];
-      }
-      const TensorPlan& t = p->tensors[lp.tensor];
-      g.tensor = lp.tensor;
-      g.dst_off = (int64_t)(t.off * (uint64_t)B / 8);
-      r->gd_fwd.push_back(g);
-      g.dst_off = (int64_t)(t.goff * (uint64_t)B / 8);
-      r->gd_grad.push_back(g);
-      g.dst_off = (int64_t)(t.gcot * (uint64_t)B / 8);
-      r->gd_gcot.push_back(g);
-      r->max_leaf_elems = std::max(r->max_leaf_elems, 1 << lp.rank);
-      if (lp.param >= 0) r->pl.push_back(ParamLeaf{lp.src_off, lp.param, gi});
-      ++gi;
-    }
-    r->n_pl = (int)r->pl.size();
-    for (auto& pr : p->out_sliced) {
-      r->sl_bits.push_back(pr.first);
-      r->out_bits.push_back(pr.second);
-    }
-    require(r->sl_bits.size() <= 32, "more than 32 sliced open indices");
-    // kernel choice per mode and step (refined by ltn_autotune)
-    for (int mode = 0; mode < 3; ++mode)
-      for (auto& sp : p->steps) {
-        ltn_plan_impl::Choice ch;
-        ch.tk = default_tk(sp.k, (1ull << (sp.m + sp.n)) * (uint64_t)B);
-        if (sp.kernel == LTN_K_MFMA) {
-          // MFMA columns follow the output's lowest bits when possible
-          bool nat = (sp.c_mask_a & 1) != 0;
-          for (int kind : {mode == LTN_C64 ? 1 : 2, 1}) {
-            int km = kind == 2 ? mode : LTN_C64;
-            for (bool sw : {nat, !nat}) {
-              int c = sw ? default_cfg(sp.n, sp.k, sp.m, km) : default_cfg(sp.m, sp.k, sp.n, km);
-              if (c >= 0 && ch.kind == 0) {
-                ch.kind = kind;
-                ch.cfg = c;
-                ch.swap = sw;
-              }
-            }
-          }
-        }
-        // few outputs and a long sum: split the sum over blocks
-        if (ch.kind == 0 && skinny_fits(sp.m, sp.k, sp.n) && sp.k >= 10) {
-          ch.kind = 4;
-          ch.cfg = 0;
-        }
-        // steps with many output rows and no MFMA tile: the narrow kernel
-        if (ch.kind == 0 && sp.m + sp.n >= 12) {
-          bool sw = sp.n > sp.m;
-          if (sw ? narrow_fits(sp.n, sp.k, sp.m) : narrow_fits(sp.m, sp.k, sp.n)) {
-            ch.kind = 3;
-            ch.cfg = 0;
-            ch.swap = sw;
-          }
-        }
-        r->choice[mode].push_back(ch);
-      }
-    r->needs_grad.assign(p->tensors.size(), 0);
-    for (size_t v = 0; v < p->tensors.size(); ++v) {
-      if ((int)v < p->L)
-        r->needs_grad[v] = p->leaves[v].param >= 0;
-      else {
-        const StepPlan& sp = p->steps[v - p->L];
-        r->needs_grad[v] = r->needs_grad[sp.left] || r->needs_grad[sp.right];
-      }
-    }
-    // uploads (host vectors live in the plan / impl; synchronised below)
-    HIPCHECK(hipMemcpyAsync(r->ws + r->lay.leafdata, p->leaf_data.data(), (size_t)p->leaf_elems * 8,
-                            hipMemcpyHostToDevice, r->st));
-    HIPCHECK(hipMemcpyAsync(r->ws + r->lay.gd_fwd, r->gd_fwd.data(), r->gd_fwd.size() * sizeof(GatherDesc),
-                            hipMemcpyHostToDevice, r->st));
-    if (grad) {
-      HIPCHECK(hipMemcpyAsync(r->ws + r->lay.gd_grad, r->gd_grad.data(),
-                              r->gd_grad.size() * sizeof(GatherDesc), hipMemcpyHostToDevice, r->st));
-      HIPCHECK(hipMemcpyAsync(r->ws + r->lay.gd_gcot, r->gd_gcot.data(),
-                              r->gd_gcot.size() * sizeof(GatherDesc), hipMemcpyHostToDevice, r->st));
-    }
-    if (r->n_pl)
-      HIPCHECK(hipMemcpyAsync(r->ws + r->lay.pl, r->pl.data(), r->pl.size() * sizeof(ParamLeaf),
-                              hipMemcpyHostToDevice, r->st));
-    HIPCHECK(hipStreamSynchronize(r->st));
+    bind_state(p, r, reinterpret_cast<char*>(d_ws), bytes, grad, reinterpret_cast<hipStream_t>(stream), B);
   });
 }
 
@@ -726,6 +747,75 @@ extern "C" ltn_status ltn_execute(ltn_plan* p, const uint64_t* ids, uint64_t n, 
 extern "C" ltn_status ltn_execute_range(ltn_plan* p, uint64_t begin, uint64_t end, int32_t mode,
                                         void* d_out) {
   return execute_impl(p, nullptr, begin, end, true, mode, d_out);
+}
+
+// Device memory of the library's own, for callers that cannot allocate:
+// one fixed array per GPU, held until the process ends. Host code never
+// uses the array's name as an address (on the host it is only a handle);
+// it uses the device address hipGetSymbolAddress returns for the current
+// device, fetched once per device.
+static __device__ __align__(256) char scratch[LTN_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+char* scratch_ptr() {
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  require(dev >= 0 && dev < kMaxDevices, "device ordinal above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    require(ptr != nullptr, "no device address for the scratch array");
+    g_scratch_ptr[dev] = reinterpret_cast<char*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" ltn_status ltn_execute_scratch(ltn_plan* p, const uint64_t* ids, uint64_t n, int32_t mode,
+                                          void* d_out, void* stream) {
+  return guarded([&] {
+    require(p != nullptr, "plan is NULL");
+    check_mode(mode);
+    require(d_out != nullptr, "d_out is NULL");
+    require(n == 0 || ids != nullptr, "slice_ids is NULL");
+    const int ns = (int)p->sliced.size();
+    if (ns < 64)
+      for (uint64_t i = 0; i < n; ++i)
+        require(ids[i] < (1ull << ns), "slice id " + std::to_string(ids[i]) + " is not below 2^|S|");
+    if (n == 0) return;
+    const int B = fit_batch(p, LTN_SCRATCH_BYTES, 0, (int)std::min<uint64_t>(n, 4096));
+    if (B == 0)
+      fail(LTN_E_NOMEM, "one slice needs " + std::to_string(layout(p, 1, 0).total) +
+                            " bytes of workspace; the library's scratch holds " +
+                            std::to_string((size_t)LTN_SCRATCH_BYTES));
+    char* ws = scratch_ptr();
+    // a state of this call only: the plan's own binding (if any) is kept
+    ltn_plan_impl tmp;
+    ltn_plan_impl* bound = p->rt;
+    p->rt = &tmp;
+    try {
+      bind_state(p, &tmp, ws, LTN_SCRATCH_BYTES, 0, reinterpret_cast<hipStream_t>(stream), B);
+      build_fwd_seq(p, mode);
+      for (uint64_t off = 0; off < n; off += (uint64_t)B) {
+        const int nb = (int)std::min<uint64_t>((uint64_t)B, n - off);
+        set_ids(p, ids + off, 0, nb, false);
+        enqueue_forward(p, nb, false, mode);
+        enqueue_reduce(p, nb, false, reinterpret_cast<double*>(d_out));
+        check_launch();
+      }
+    } catch (...) {
+      p->rt = bound;
+      throw;
+    }
+    p->rt = bound;
+  });
 }
 
 extern "C" ltn_status ltn_set_params(ltn_plan* p, const double* d_angles) {

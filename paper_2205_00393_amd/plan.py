@@ -133,6 +133,16 @@ class Plan:
                                           C.c_void_p(out.data_ptr())))
         return out
 
+    def execute_scratch(self, slice_ids, out=None, mode: str = "c64", stream=None):
+        """Add the listed slices into ``out`` using the library's own device
+        scratch (no workspace, no allocation by the library)."""
+        if out is None:
+            out = self.new_output()
+        ids = np.ascontiguousarray(np.asarray(slice_ids, dtype=np.uint64).reshape(-1))
+        L.check(L.lib().ltn_execute_scratch(self._h, ids.ctypes.data_as(C.POINTER(C.c_uint64)), len(ids),
+                                            L.MODES[mode], C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
     def set_params(self, angles):
         """angles: float64 CUDA tensor [n_params] laid out [gate][a, b, c]."""
         a = angles.contiguous()
