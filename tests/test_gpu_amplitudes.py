@@ -99,15 +99,21 @@ def test_slice_enumeration_matches_oracle(torch):
     assert nonzero >= 2
 
 
-def test_sliced_open_indices_are_placed(torch):
-    """Slicing an open index places each slice's block instead of summing."""
+@pytest.mark.parametrize("batch", [2, 5, 16])
+def test_sliced_open_indices_are_placed(torch, batch):
+    """Slicing an open index places each slice's block instead of summing.
+    Two open and two closed indices are sliced: 16 slices in 4 groups that
+    share their sliced open bits (and so their targets). Batches of 5 and 16
+    take the one-wave-per-element FP64 sum (equal targets summed in lane
+    order, written once per target), batches of 2 the per-element loop."""
     import paper_2205_00393_amd as P
     w = _reduced(rows=3, cols=4, cycles=8, n_open=4, t=-1)
     pr = P.prepare(w, alphas=(1.0,), taus=(0.0,), n_seeds=1)
     net = pr.net
-    S = [net.open_ids[1], net.open_ids[3]] + [x for x in pr.sliced]
+    closed = [x for x in range(net.n_indices) if x not in net.open_ids][:2]
+    S = [net.open_ids[1], closed[0], net.open_ids[3], closed[1]] + [x for x in pr.sliced]
     plan = P.Plan(net, pr.path, S)
-    plan.bind(batch=2)
+    plan.bind(batch=batch)
     out = plan.execute_range(0, 1 << len(S))
     torch.cuda.synchronize()
     assert rel_l2(out.cpu().numpy(), _sv(w)) < TOL_C64
@@ -283,11 +289,11 @@ def test_rqc30_split_full_size(torch, mode):
 
 
 def test_rqc53_sampled_slice(torch):
-    """53-qubit workload at full size (t = 30, |S| = 68): one sampled slice
-    (2^20 amplitudes) in complex64, split fp16 and split bf16 against the
-    oracle's complex128 contraction of the same slice, stored by
-    tests/golden/make_rqc53_reference.py (4096 seeded amplitudes and the
-    block's squared norm)."""
+    """53-qubit workload at full size (t = 30, |S| = 68): the first two
+    slices of the seeded subset (2^20 amplitudes each) in complex64, split
+    fp16 and split bf16 against the oracle's complex128 contraction of the
+    same slices, stored by tests/golden/make_rqc53_reference.py: element by
+    element on 2^16 seeded output positions, and the block's squared norm."""
     import paper_2205_00393_amd as P
     path = os.path.join(GOLDEN, "rqc53_slices.npz")
     if not os.path.exists(path):
@@ -298,6 +304,7 @@ def test_rqc53_sampled_slice(torch):
     banner("rqc53 plan")
     pr = P.prepare(w)
     assert pr.sliced == meta["sliced"]
+    assert len(meta["slices"]) >= 2
     plan = pr.plan()
     plan.bind(batch=1)
     for j, rec in enumerate(meta["slices"]):
@@ -315,9 +322,10 @@ def test_rqc53_sampled_slice(torch):
 
 
 def test_rqc53_reconfigured_sampled_slice(torch):
-    """53-qubit workload on the reconfigured path (t = 30): one sampled
-    slice in all three modes against the oracle's complex128 contraction of
-    the same slice
+    """53-qubit workload on the reconfigured path (t = 30): the first two
+    slices of the seeded subset in all three modes against the oracle's
+    complex128 contraction of the same slices, element by element on the
+    stored seeded output positions
     (tests/golden/make_rqc53_reference.py --reconf 8)."""
     import paper_2205_00393_amd as P
     path = os.path.join(GOLDEN, "rqc53_reconf_slices.npz")
