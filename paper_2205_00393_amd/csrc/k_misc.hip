@@ -87,9 +87,13 @@ __device__ __forceinline__ uint64_t placement(uint64_t e, uint64_t out_mask, con
   return p;
 }
 
-// out[place(s_b, e)] += root[b][e] in FP64, b in ascending order; one
-// thread per root element owns every target it writes (placement is
-// injective in e for a fixed slice), so there are no races.
+// out[place(s_b, e)] += root[b][e] in FP64. Two forms, both in a fixed
+// order (reruns are bit-identical) and without atomics: every target an
+// element e can reach has e's unsliced open bits, so the work of one e
+// never meets another's.
+//
+// Large roots: one thread per root element, b in ascending order (reads
+// coalesced along e).
 __global__ void k_reduce(const float2* __restrict__ root, int rank, uint64_t out_mask, SliceOut so,
                          int n_sl, const uint64_t* __restrict__ ids, int nb, double* out) {
   int64_t n = int64_t(1) << rank;
@@ -111,6 +115,79 @@ __global__ void k_reduce(const float2* __restrict__ root, int rank, uint64_t out
         uint64_t p = placement((uint64_t)e, out_mask, so, n_sl, ids[b]);
         out[2 * p] += (double)v.x;
         out[2 * p + 1] += (double)v.y;
+      }
+    }
+  }
+}
+
+// Small roots and many slices: one wave per root element, the batch
+// across its lanes 64 slices at a time. Without sliced open indices every
+// slice adds into the same target: a fixed butterfly of FP64 shuffles sums
+// each chunk, lane 0 adds the chunks in order and writes once. With sliced
+// open indices a slice's target also carries its sliced open bits (its
+// key): each lane adds, in ascending lane order, the values of the lanes
+// with its key, and the lowest lane of each key writes; blocks are one
+// wave and chunks are separated by a barrier, so a chunk sees the writes
+// of the chunks before it.
+__global__ void __launch_bounds__(64) k_reduce_lanes(const float2* __restrict__ root, int rank,
+                                                     uint64_t out_mask, SliceOut so, int n_sl,
+                                                     const uint64_t* __restrict__ ids, int nb,
+                                                     double* out) {
+  const int lane = threadIdx.x;
+  const int64_t n = int64_t(1) << rank;
+  for (int64_t e = blockIdx.x; e < n; e += gridDim.x) {
+    const uint64_t base = pdep((uint64_t)e, out_mask);
+    if (n_sl == 0) {
+      double re = 0, im = 0;
+      for (int c = 0; c < nb; c += 64) {
+        const int b = c + lane;
+        double xr = 0, xi = 0;
+        if (b < nb) {
+          const float2 v = root[(int64_t)b * n + e];
+          xr = v.x;
+          xi = v.y;
+        }
+        for (int off = 1; off < 64; off <<= 1) {
+          xr += __shfl_xor(xr, off);
+          xi += __shfl_xor(xi, off);
+        }
+        re += xr;
+        im += xi;
+      }
+      if (lane == 0) {
+        out[2 * base] += re;
+        out[2 * base + 1] += im;
+      }
+    } else {
+      for (int c = 0; c < nb; c += 64) {
+        const int b = c + lane;
+        const bool mine = b < nb;
+        double xr = 0, xi = 0;
+        unsigned long long key = ~0ull;
+        if (mine) {
+          const float2 v = root[(int64_t)b * n + e];
+          xr = v.x;
+          xi = v.y;
+          key = placement(0, 0, so, n_sl, ids[b]);
+        }
+        double sr = 0, si = 0;
+        bool lowest = true;
+        const int lim = nb - c < 64 ? nb - c : 64;
+        for (int i = 0; i < lim; ++i) {
+          const unsigned long long ki = __shfl(key, i);
+          const double vr = __shfl(xr, i), vi = __shfl(xi, i);
+          if (ki == key) {
+            sr += vr;
+            si += vi;
+            if (i < lane) lowest = false;
+          }
+        }
+        if (mine && lowest) {
+          const uint64_t p = base | key;
+          out[2 * p] += sr;
+          out[2 * p + 1] += si;
+        }
+        __syncthreads();
       }
     }
   }
@@ -357,8 +434,12 @@ void launch_reduce(const float2* root, int rank, uint64_t out_mask, const int32_
                    const int32_t* out_bits, int n_sl, const uint64_t* ids, int nb, double* out,
                    hipStream_t st) {
   uint64_t n = 1ull << rank;
-  hipLaunchKernelGGL(k_reduce, dim3(grid_for(n, 256)), dim3(256), 0, st, root, rank, out_mask,
-                     make_so(sl_bits, out_bits, n_sl), n_sl, ids, nb, out);
+  if (nb >= 4 && n <= 4096)
+    hipLaunchKernelGGL(k_reduce_lanes, dim3((unsigned)n), dim3(64), 0, st, root, rank, out_mask,
+                       make_so(sl_bits, out_bits, n_sl), n_sl, ids, nb, out);
+  else
+    hipLaunchKernelGGL(k_reduce, dim3(grid_for(n, 256)), dim3(256), 0, st, root, rank, out_mask,
+                       make_so(sl_bits, out_bits, n_sl), n_sl, ids, nb, out);
 }
 
 void launch_root_cotangent(const double* cot, int rank, uint64_t out_mask, const int32_t* sl_bits,

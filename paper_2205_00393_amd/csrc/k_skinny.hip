@@ -7,7 +7,8 @@
 // for every output (coalesced reads of all 2^m rows of A and 2^n rows of B,
 // FP32 accumulators in registers, then a wave and block reduction), writes
 // one FP32 partial per output; a second kernel adds the partials of each
-// output in FP64, in chunk order, so the result does not depend on timing.
+// output in FP32 in a fixed order (strided per thread, then a pairwise tree
+// over the block), so the result does not depend on timing.
 #include "kernels.h"
 
 namespace ltn {
@@ -78,18 +79,19 @@ __global__ __launch_bounds__(kThreads) void k_skinny_partial(SkinnyDesc d, int k
   }
 }
 
-// One block per (output, slice): the chunk partials are added in FP64 in a
-// fixed order (strided per thread, then a tree over the block).
+// One block per (output, slice): the chunk partials are added in FP32 in a
+// fixed order (at most 16 per thread, strided, then a pairwise tree over
+// the block).
 __global__ __launch_bounds__(kThreads) void k_skinny_reduce(SkinnyDesc d, int64_t chunks) {
   const int e = blockIdx.x, b = blockIdx.y;
   const int mn = 1 << (d.m + d.n);
-  double x = 0.0, y = 0.0;
+  float x = 0.f, y = 0.f;
   for (int64_t c = threadIdx.x; c < chunks; c += kThreads) {
     const float2 v = d.part[(b * chunks + c) * mn + e];
     x += v.x;
     y += v.y;
   }
-  __shared__ double rx[kThreads], ry[kThreads];
+  __shared__ float rx[kThreads], ry[kThreads];
   rx[threadIdx.x] = x;
   ry[threadIdx.x] = y;
   __syncthreads();
@@ -104,7 +106,7 @@ __global__ __launch_bounds__(kThreads) void k_skinny_reduce(SkinnyDesc d, int64_
     const uint64_t full = (1ull << (d.m + d.n)) - 1;
     const uint64_t i = (uint64_t)e >> d.n, j = (uint64_t)e & ((1ull << d.n) - 1);
     const uint64_t addr = pdep_s(i, d.cmask) | pdep_s(j, ~d.cmask & full);
-    const float2 out = make_float2((float)rx[0], (float)ry[0]);
+    const float2 out = make_float2(rx[0], ry[0]);
     d.C[b * d.sC + addr] = out;
     if (d.scale_c) raise_max(d.scale_c + b, fmaxf(fabsf(out.x), fabsf(out.y)));
   }
