@@ -1202,12 +1202,12 @@ void write_cache(const char* path, const std::map<std::string, std::pair<int, in
   f << "}\n";
 }
 
-float time_step(ltn_plan* p, int s, int reps, int mode) {
+float time_step(ltn_plan* p, int s, int reps, int mode, bool warm = true) {
   auto& r = *p->rt;
   hipEvent_t a, b;
   HIPCHECK(hipEventCreate(&a));
   HIPCHECK(hipEventCreate(&b));
-  enqueue_step(p, s, r.B, false, mode);  // untimed warm-up launch
+  if (warm) enqueue_step(p, s, r.B, false, mode);  // untimed warm-up launch
   HIPCHECK(hipEventRecord(a, r.st));
   for (int i = 0; i < reps; ++i) enqueue_step(p, s, r.B, false, mode);
   HIPCHECK(hipEventRecord(b, r.st));
@@ -1321,14 +1321,22 @@ extern "C" ltn_status ltn_autotune(ltn_plan* p, int32_t mode, const char* cache_
               cands.push_back(ch);
             }
       }
+      // one launch of each candidate; clearly slower ones get no repeats,
+      // short launches (timer and launch noise) three more, long ones one
+      // more only when they come within 5 % of the best so far
       float best = 1e30f;
       Choice pick = cands[0];
+      bool first = true;
       for (auto& c : cands) {
         r.choice[mode][s] = c;
         if (cands.size() == 1) break;
-        float once = time_step(p, s, 1, mode);
-        if (once > 3.0f * best) continue;  // clearly slower: no repeats
-        float ms = std::min(once, time_step(p, s, 2, mode));
+        float ms = time_step(p, s, 1, mode, first);
+        first = false;
+        if (ms > 2.0f * best) continue;
+        if (ms < 2.0f)
+          ms = std::min(ms, time_step(p, s, 3, mode, false));
+        else if (ms < 1.05f * best)
+          ms = std::min(ms, time_step(p, s, 1, mode, false));
         if (ms < best) {
           best = ms;
           pick = c;
