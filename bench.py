@@ -1,11 +1,22 @@
-"""Benchmark: sliced contraction of the 30-qubit random circuit on one GPU.
+"""Benchmark: sliced contraction of random quantum circuits on one GPU.
 
-One step = the whole hot path over every slice of the workload (leaf
-gather, all contraction steps, FP64 slice sum) into a zeroed output.
-Prints one JSON line (see the keys below). Inputs are synthetic (seeded
-circuit); the host planner runs before the timed region.
+Headline workload (default): the 53-qubit circuit (6x9 grid minus one
+site, 20 cycles, 2^20 open amplitudes) on its randomised greedy path,
+sliced by Algorithm 1 under rank 30. One step = the whole hot path (leaf
+gather, every contraction step, FP64 slice sum) over one batch of slices
+taken in order from the seeded subset of 1024 slice ids; successive steps
+walk the subset. complex64 is the headline; split fp16 and split bf16 are
+timed beside it; each mode states its error on the stored oracle slices.
+
+Extra keys: the 30-qubit workload (every slice per step, greedy and
+reconfigured paths, fused sub-paths), the 20-qubit gradient workload, and
+CPU oracle timings of each.
+
+Prints one JSON line. Inputs are synthetic (seeded circuits); the host
+planner runs before the timed regions.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -19,15 +30,20 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_MFMA_TFLOPS = 157.3   # MI355X dense FP32 matrix
 PEAK_F16_MFMA_TFLOPS = 2516.6   # MI355X dense FP16 / BF16 matrix
 PEAK_HBM_GBS = 8000.0
-GOLDEN = os.path.join(ROOT, "tests", "golden", "rqc30_amplitudes.npy")
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+TOL = {"c64": 1e-4, "split_f16": 5e-4, "split_bf16": 5e-4}
+WORKLOAD_TEXT = {
+    "rqc53": "rqc53: 6x9 grid minus site (5,8), 20 cycles, 20 open qubits (2^20 amplitudes), max rank 30",
+    "rqc30": "rqc30: 5x6 grid, 14 cycles, 6 open qubits (64 amplitudes), max rank 26",
+}
 
 
-def counter_traffic(mode):
+def counter_traffic(workload, mode):
     """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, or None when the kernel source has changed
-    since the counters were taken (or no summary exists for this mode)."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_cgemm_{'c64' if mode == 'c64' else 'split'}__rqc30_{mode}.json")
+    rocprofv3 counter summary for this workload and mode, or None when there
+    is none or the kernel source has changed since the counters were taken."""
+    kern = "k_cgemm_c64" if mode == "c64" else "k_cgemm_split"
+    path = os.path.join(ROOT, "profiles", f"{kern}__{workload}_{mode}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -46,28 +62,295 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(budget_s=30.0):
-    """The oracle (numpy complex128 tensordot) contracting slice 0 of the
-    same workload along its own path and slicing set."""
-    from oracle import network as onw, planner as opl
-    from workload import make_workload
+def host_cpu():
+    """CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    cores = len(os.sched_getaffinity(0))
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
-        threads = len(os.sched_getaffinity(0))
+        blas = None
+    return model, cores, blas
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# ---------------------------------------------------------------- CPU oracle
+def cpu_rqc53(S, t_cpu=27, budget_s=20.0):
+    """The oracle contracting sub-slices of one sampled slice of the 53-qubit
+    workload (complex128 tensordot), as many as fit in ``budget_s``, along
+    the oracle's own path (its path search takes minutes in Python, so the
+    path is the one the reference script stored, searched by the oracle).
+    The slice is cut further at rank ``t_cpu`` so that one sub-slice takes
+    seconds."""
+    from oracle import network as onw, planner as opl
+    from workload import make_workload
+    meta_path = os.path.join(GOLDEN, "rqc53_slices.json")
+    if not os.path.exists(meta_path):
+        return None
+    meta = json.load(open(meta_path))
+    if "path" not in meta or list(S) != meta["sliced"]:
+        log("cpu baseline: no stored oracle path for this slicing set; skipped")
+        return None
+    path = [tuple(p) for p in meta["path"]]
+    w = make_workload("rqc53")
+    net = onw.absorb_small(onw.circuit_network(w.circuit, w.open_qubits, w.closed_bits))
+    tree = opl.Tree(net.indices, path)
+    S2 = opl.slice_finder(tree, t_cpu, pre=meta["sliced"])
+    n_sub = 1 << (len(S2) - len(S))
+    macs_sub = tree.sliced_cost(S2) >> len(S2)
+    macs_slice = tree.sliced_cost(S) >> len(S)
+    s = int(meta["slices"][0]["id"])
+    model, cores, blas = host_cpu()
+    t0 = time.perf_counter()
+    done = 0
+    while done < n_sub and (done == 0 or time.perf_counter() - t0 < budget_s):
+        onw.slice_output(net, path, S2, s | (done << len(S)))
+        done += 1
+    dt = time.perf_counter() - t0
+    rate = 8.0 * macs_sub * done / dt
+    return {"value": rate / 1e12, "unit": "TFLOP/s", "cores": cores,
+            "blas_threads": blas, "cpu_model": model, "kind": "oracle",
+            "sec_per_slice": 8.0 * macs_slice / rate,
+            "sec_per_slice_as_subsliced": dt / done * n_sub,
+            "sample": (f"{done} of the {n_sub} sub-slices (rank cap {t_cpu}) of slice {s} of rqc53, "
+                       f"{macs_sub:.3e} complex MACs each, numpy complex128 tensordot along the "
+                       f"oracle's path; sec_per_slice = one slice's {macs_slice:.3e} MACs at that "
+                       "rate, sec_per_slice_as_subsliced = all sub-slices of the slice at that "
+                       "rate (cutting at rank 27 adds work)")}
+
+
+def cpu_rqc30(budget_s=30.0):
+    """The oracle contracting slice 0 of the 30-qubit workload along its own
+    path and slicing set."""
+    from oracle import network as onw, planner as opl
+    from workload import make_workload
     w = make_workload("rqc30")
     net = onw.absorb_small(onw.circuit_network(w.circuit, w.open_qubits, w.closed_bits))
     path, S, _ = opl.path_search(net.indices, w.max_rank, (), (0.5, 1.0, 2.0), (0.0, 0.3, 1.0), 16)
     tree = opl.Tree(net.indices, path)
     macs = tree.sliced_cost(S) >> len(S)
+    model, cores, blas = host_cpu()
     t0 = time.perf_counter()
     onw.slice_output(net, path, S, 0)
     dt = time.perf_counter() - t0
-    return {"value": 8.0 * macs / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads),
-            "kind": "oracle", "sec_per_slice": dt,
+    return {"value": 8.0 * macs / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "blas_threads": blas,
+            "cpu_model": model, "kind": "oracle", "sec_per_slice": dt,
             "sample": f"1 of {1 << len(S)} slices of rqc30 (slice 0, {macs:.3e} complex MACs), "
                       "numpy complex128 tensordot along the oracle's own path"}
+
+
+def cpu_gradient():
+    """The oracle's state-vector adjoint of the 20-qubit u3 workload: loss
+    over 256 bitstrings and its gradient in all 720 angles."""
+    from oracle import gradients as gr
+    from workload import make_workload
+    w = make_workload("rqc20_grad")
+    model, cores, blas = host_cpu()
+    t0 = time.perf_counter()
+    gr.sv_adjoint(w.circuit, w.bitstrings)
+    dt = time.perf_counter() - t0
+    return {"ms_fwd_bwd": sig6(dt * 1e3), "cores": cores, "blas_threads": blas, "cpu_model": model,
+            "kind": "oracle", "sample": "state-vector adjoint (complex128), all 720 angles"}
+
+
+# ---------------------------------------------------------------- GPU legs
+def time_plan(torch, P, pr, workload, modes, args, tag, fuse_rank=0, golden=None):
+    """Bind a prepared plan and time each mode on it.
+
+    rqc30: a step is every slice. rqc53: a step is one batch of slices from
+    the seeded 1024-id subset, successive steps walking it. ``golden``
+    (positions, per-slice amplitudes, slice ids, squared norms) gives each
+    mode's error on those slices, run one at a time after the timed steps."""
+    from workload import sample_slice_ids
+    t0 = time.perf_counter()
+    plan = pr.plan(fuse_rank=fuse_rank)
+    costs = P.tree_costs(pr.net, pr.path, pr.sliced)
+    info = plan.info()
+    macs_slice = info["macs_per_slice"]
+    steps = plan.steps()
+    free = torch.cuda.mem_get_info()[0]
+    if workload == "rqc30":
+        ids = None
+        batch = plan.bind(batch=1 << len(pr.sliced))
+        per_step = 1 << len(pr.sliced)
+    else:
+        ids = np.asarray(sample_slice_ids(len(pr.sliced), 1024, 3), dtype=np.uint64)
+        b = 1
+        while b < len(ids) and plan.workspace_size(b + 1) < 0.75 * free:
+            b += 1
+        batch = plan.bind(batch=b)
+        per_step = batch
+    log(f"[{tag}] plan compiled and bound in {time.perf_counter() - t0:.2f}s: |S|={len(pr.sliced)} "
+        f"C(B,S)=2^{costs.log2_sliced:.2f} per-slice MACs={macs_slice:.3e} batch={batch} "
+        f"workspace={plan.workspace_size(batch) / 2**30:.2f} GiB")
+    flops_step = 8.0 * macs_slice * per_step
+
+    def batch_ids(j):
+        lo = (j * per_step) % len(ids)
+        sel = ids[lo:lo + per_step]
+        if len(sel) < per_step:
+            sel = np.concatenate([sel, ids[:per_step - len(sel)]])
+        return sel
+
+    def run_step(out, mode, j):
+        if ids is None:
+            plan.execute_range(0, per_step, out, mode)
+        else:
+            plan.execute(batch_ids(j), out, mode)
+
+    def measure(mode):
+        t0 = time.perf_counter()
+        plan.autotune(mode, args.tune_cache)
+        log(f"[{tag}/{mode}] autotuned in {time.perf_counter() - t0:.2f}s")
+        out = plan.new_output()
+        for j in range(args.warmup):
+            out.zero_()
+            run_step(out, mode, j)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(args.warmup, args.warmup + args.steps):
+            out.zero_()
+            run_step(out, mode, j)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res = {"tflops": flops_step * args.steps / dt / 1e12, "ms_per_step": 1e3 * dt / args.steps,
+               "sec_per_slice": dt / args.steps / per_step}
+        if golden is not None and ids is None:
+            res["rel_l2_error"] = rel_l2(out.cpu().numpy(), golden["amplitudes"])
+        elif golden is not None:
+            errs, n2err = [], []
+            for s, amp, n2 in zip(golden["ids"], golden["amplitudes"], golden["norm2"]):
+                out.zero_()
+                plan.execute([s], out, mode)
+                got = out.cpu().numpy()
+                errs.append(rel_l2(got[golden["positions"]], amp))
+                n2err.append(abs(float(np.sum(np.abs(got) ** 2)) - n2) / n2)
+            res["rel_l2_error"] = max(errs)
+            res["rel_l2_error_per_slice"] = [sig6(e) for e in errs]
+            res["norm2_rel_error_per_slice"] = [sig6(e) for e in n2err]
+        # the dominant kernel (the MFMA complex GEMM): live per-step HIP
+        # events on the plan's stream (a replay of one batch outside the graph)
+        ms = np.zeros(len(steps))
+        reps = 3
+        first = 0 if ids is None else int(ids[0])
+        for _ in range(reps):
+            ms += plan.profile_steps(first, mode)
+        ms /= reps
+        mf_flops, mf_bytes, mf_ms, mf_launch, split_flops = 0.0, 0.0, 0.0, 0, 0.0
+        for k, st in enumerate(steps):
+            kind, _, _, _ = plan.step_kernel(k, mode)
+            if kind in (1, 2):
+                f = 8.0 * (1 << (st["m"] + st["k"] + st["n"])) * batch
+                mf_flops += f
+                mf_bytes += 8.0 * ((1 << (st["m"] + st["k"])) + (1 << (st["n"] + st["k"])) +
+                                   (1 << (st["m"] + st["n"]))) * batch
+                mf_ms += ms[k]
+                mf_launch += 1
+                if kind == 2:
+                    split_flops += f
+        res["mfma_flops_per_batch"] = mf_flops
+        res["mfma_alg_bytes_per_batch"] = mf_bytes
+        res["mfma_ms_per_batch"] = mf_ms
+        res["step_ms_per_batch"] = float(ms.sum())
+        res["mfma_launches_per_batch"] = mf_launch
+        res["mfma_tflops"] = mf_flops / (mf_ms * 1e-3) / 1e12 if mf_ms > 0 else 0.0
+        res["split_mac_fraction"] = split_flops / (8.0 * macs_slice * batch)
+        log(f"[{tag}/{mode}] {res['ms_per_step']:.2f} ms/step, {res['tflops']:.2f} TFLOP/s, "
+            f"MFMA {mf_ms:.2f} of {res['step_ms_per_batch']:.2f} ms per batch "
+            f"({res['mfma_tflops']:.2f} TFLOP/s), err {res.get('rel_l2_error')}")
+        return res
+
+    results = {m: measure(m) for m in modes}
+    facts = dict(per_step=per_step, batch=batch, costs=costs, macs_slice=macs_slice,
+                 flops_step=flops_step, n_sliced=len(pr.sliced), groups=plan.groups())
+    del plan
+    torch.cuda.empty_cache()
+    return results, facts
+
+
+def mode_table(results):
+    out = {}
+    for m, r in results.items():
+        out[m] = {k: (sig6(v) if not isinstance(v, list) else v) for k, v in r.items()}
+        out[m]["speedup_vs_c64"] = round(r["tflops"] / results["c64"]["tflops"], 4) if "c64" in results else None
+        out[m]["meets_tolerance"] = (r.get("rel_l2_error") is not None and r["rel_l2_error"] <= TOL[m])
+    return out
+
+
+def roofline_of(workload, mode, r):
+    if mode == "c64":
+        peak, achieved = PEAK_FP32_MFMA_TFLOPS, r["mfma_tflops"]
+    else:
+        # split: three fp16/bf16 matrix products per real product; executed
+        # matrix flops are 3x the algorithmic count
+        peak, achieved = PEAK_F16_MFMA_TFLOPS, 3.0 * r["mfma_tflops"]
+    return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": counter_traffic(workload, mode),
+            "kernel": "k_cgemm_c64" if mode == "c64" else "k_cgemm_split",
+            "launches_per_batch": r["mfma_launches_per_batch"],
+            "share_of_step_time": round(r["mfma_ms_per_batch"] / r["step_ms_per_batch"], 4)}
+
+
+def rqc53_golden():
+    path = os.path.join(GOLDEN, "rqc53_slices.npz")
+    if not os.path.exists(path):
+        return None, None
+    z = np.load(path)
+    meta = json.load(open(os.path.join(GOLDEN, "rqc53_slices.json")))
+    return {"positions": z["positions"], "amplitudes": list(z["amplitudes"]),
+            "ids": [int(r["id"]) for r in meta["slices"]],
+            "norm2": [r["norm2"] for r in meta["slices"]]}, meta
+
+
+def rqc30_extra(torch, P, args):
+    """The 30-qubit workload: every slice per step on the randomised greedy
+    path (all modes), then the same circuit on the reconfigured path, with
+    and without fused sub-paths."""
+    from workload import make_workload
+    w = make_workload("rqc30")
+    ref_path = os.path.join(GOLDEN, "rqc30_amplitudes.npy")
+    golden = {"amplitudes": np.load(ref_path)} if os.path.exists(ref_path) else None
+    t0 = time.perf_counter()
+    pr = P.prepare(w)
+    t_plan = time.perf_counter() - t0
+    res, f = time_plan(torch, P, pr, "rqc30", args.rqc30_modes.split(","), args, "rqc30", golden=golden)
+    out = {"workload": WORKLOAD_TEXT["rqc30"] + ", all slices per step, randomised greedy path",
+           "plan_seconds": round(t_plan, 3), "slices": f["per_step"], "sliced_indices": f["n_sliced"],
+           "batch": f["batch"], "log2_C_BS": round(f["costs"].log2_sliced, 4),
+           "overhead": round(f["costs"].overhead, 5), "macs_per_slice": f["macs_slice"],
+           "modes": mode_table(res), "roofline": roofline_of("rqc30", "c64", res["c64"]) if "c64" in res else None}
+    if args.path_variant:
+        t0 = time.perf_counter()
+        prv = P.prepare(w, reconf_k=10)
+        t_plan = time.perf_counter() - t0
+        vres, vf = time_plan(torch, P, prv, "rqc30", args.path_variant.split(","), args, "rqc30 reconf",
+                             golden=golden)
+        var = {"path": "randomised greedy + subtree reconfiguration (k=10)", "plan_seconds": round(t_plan, 3),
+               "sliced_indices": vf["n_sliced"], "log2_C_BS": round(vf["costs"].log2_sliced, 4),
+               "macs_per_slice": vf["macs_slice"],
+               "modes": {m: {k: sig6(v) for k, v in r.items()} for m, r in vres.items()}}
+        for m, r in vres.items():
+            if m in res:
+                var["modes"][m]["time_to_solution_speedup_vs_greedy_path"] = round(
+                    res[m]["ms_per_step"] / r["ms_per_step"], 3)
+        fres, ff = time_plan(torch, P, prv, "rqc30", ["c64"], args, "rqc30 reconf+fused", fuse_rank=10,
+                             golden=golden)
+        var["fused_sub_paths"] = {"fuse_rank": 10, "groups": len(ff["groups"]),
+                                  "steps_fused": sum(g["n_steps"] for g in ff["groups"]),
+                                  "c64": {k: sig6(v) for k, v in fres["c64"].items()}}
+        out["path_variant"] = var
+    return out
 
 
 def gradient_leg(torch, P, args):
@@ -103,13 +386,151 @@ def gradient_leg(torch, P, args):
                        "loss over 256 bitstrings (one slice each)",
            "batch": batch, "ms_fwd_bwd": sig6(dt * 1e3),
            "ms_per_bitstring": sig6(dt * 1e3 / len(ids))}
-    ref_path = os.path.join(ROOT, "tests", "golden", "rqc20_grad_reference.npz")
+    ref_path = os.path.join(GOLDEN, "rqc20_grad_reference.npz")
     if os.path.exists(ref_path):
         ref = np.load(ref_path)
         gg = g.detach().cpu().numpy()
         res["grad_rel_l2_error"] = sig6(float(np.linalg.norm(gg - ref["grad"]) / np.linalg.norm(ref["grad"])))
     log(f"gradient: {res['ms_fwd_bwd']:.2f} ms forward + backward, error {res.get('grad_rel_l2_error')}")
+    del plan
+    torch.cuda.empty_cache()
     return res
+
+
+# ------------------------------------------------------- profile summaries
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)):
+        rows += [dict(r, _file=f) for r in csv.DictReader(open(f))]
+    return rows
+
+
+def _per_dispatch(d, counter, name_part=None):
+    """Counter value per dispatch (summed over the counter's dimensions),
+    for kernels whose name contains name_part (all when None)."""
+    v = {}
+    names = {}
+    for r in _csv_rows(d, "counter_collection.csv"):
+        if r["Counter_Name"] != counter or (name_part and name_part not in r["Kernel_Name"]):
+            continue
+        key = (r["_file"], r["Dispatch_Id"])
+        v[key] = v.get(key, 0.0) + float(r["Counter_Value"])
+        names[key] = r["Kernel_Name"]
+    return v, names
+
+
+def summarize_main(argv):
+    """Summarise the rocprofv3 runs of one kernel family into
+    profiles/<stem>.json and .md (run from the repository root):
+
+      python bench.py summarize --kernel k_cgemm_c64 --workload rqc53 --mode c64 \
+          --bench BENCH_LINE.json --trace DIR --fetch DIR --write DIR \
+          --copy-fetch DIR --copy-write DIR --copy-mib 1024 [--mfma DIR] \
+          --commands FILE --out profiles/STEM
+
+    The kernel trace gives the average launch duration; FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch) are scaled by what they read for a plain
+    device copy of --copy-mib MiB; the bench line of the same session gives
+    the algorithmic flops and bytes per batch of the kernel family."""
+    ap = argparse.ArgumentParser(prog="bench.py summarize")
+    for a in ("--kernel", "--workload", "--mode", "--bench", "--trace", "--fetch", "--write",
+              "--copy-fetch", "--copy-write", "--commands", "--out"):
+        ap.add_argument(a, required=True)
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--mfma", default=None)
+    a = ap.parse_args(argv)
+    line = json.loads(open(a.bench).read().strip().splitlines()[-1])
+    r = line["modes"][a.mode] if a.workload in line["config"]["workload"] else \
+        line[a.workload]["modes"][a.mode]
+    batch = line["config"]["batch"] if a.workload in line["config"]["workload"] else line[a.workload]["batch"]
+    launches = r["mfma_launches_per_batch"]
+    flops_l = r["mfma_flops_per_batch"] / launches
+    bytes_l = r["mfma_alg_bytes_per_batch"] / launches
+    durs = [int(x["End_Timestamp"]) - int(x["Start_Timestamp"])
+            for x in _csv_rows(a.trace, "kernel_trace.csv") if a.kernel in x["Kernel_Name"]]
+    avg_ms = sum(durs) / len(durs) / 1e6
+    copy_bytes = a.copy_mib << 20
+    cf, cfn = _per_dispatch(a.copy_fetch, "FETCH_SIZE")
+    cw, cwn = _per_dispatch(a.copy_write, "WRITE_SIZE")
+    kf = max(cf, key=cf.get)
+    kw = max(cw, key=cw.get)
+    fetch_scale = copy_bytes / (cf[kf] * 1024.0)
+    write_scale = copy_bytes / (cw[kw] * 1024.0)
+    f, _ = _per_dispatch(a.fetch, "FETCH_SIZE", a.kernel)
+    w, _ = _per_dispatch(a.write, "WRITE_SIZE", a.kernel)
+    fetch_l = sum(f.values()) / len(f) * 1024.0 * fetch_scale
+    write_l = sum(w.values()) / len(w) * 1024.0 * write_scale
+    split = a.mode != "c64"
+    peak = PEAK_F16_MFMA_TFLOPS if split else PEAK_FP32_MFMA_TFLOPS
+    alg_tf = flops_l / (avg_ms * 1e-3) / 1e12
+    exe_tf = alg_tf * (3.0 if split else 1.0)
+    src = open(os.path.join(ROOT, "paper_2205_00393_amd", "csrc", "k_mfma.hip"), "rb").read()
+    rec = {"kernel": a.kernel, "workload": a.workload, "mode": a.mode, "batch": batch,
+           "launches_per_batch": launches, "avg_launch_ms": avg_ms, "calls": len(durs),
+           "alg_flops_per_launch": flops_l, "alg_bytes_per_launch": bytes_l,
+           "achieved_alg_tflops": alg_tf, "executed_matrix_tflops": exe_tf, "peak_tflops": peak,
+           "frac_of_peak": exe_tf / peak,
+           "hbm_fetch_bytes_per_launch": fetch_l, "hbm_write_bytes_per_launch": write_l,
+           "traffic_bytes_per_launch": fetch_l + write_l,
+           "traffic_over_algorithmic": (fetch_l + write_l) / bytes_l,
+           "fetch_scale": fetch_scale, "write_scale": write_scale,
+           "copy_kernel": cfn[kf], "source_sha256": hashlib.sha256(src).hexdigest(),
+           "bench_tflops": line["value"] if a.workload in line["config"]["workload"] else None}
+    md = [f"# {a.kernel} on the {a.workload} workload ({a.mode})", "",
+          f"Workload: {line['config']['workload'] if a.workload in line['config']['workload'] else line[a.workload]['workload']}.",
+          f"Batch of {batch} slices; tiles from the autotuner (cache written by the first command, "
+          "in the same session).", "", "## Commands (repository root, `TMPDIR=/tmp`)", "", "```",
+          open(a.commands).read().strip(), "```", ""]
+    if a.mfma:
+        inst, _ = _per_dispatch(a.mfma, "SQ_INSTS_MFMA", a.kernel)
+        busy, _ = _per_dispatch(a.mfma, "SQ_VALU_MFMA_BUSY_CYCLES", a.kernel)
+        n_inst = sum(inst.values())
+        # flops per MFMA instruction: 32x32x2 FP32 = 4096, 32x32x16 f16/bf16 = 32768
+        fpi = 32768 if split else 4096
+        mc = {"dispatches": len(inst), "mfma_instructions": n_inst, "flops_per_instruction": fpi,
+              "executed_flops": n_inst * fpi, "SQ_VALU_MFMA_BUSY_CYCLES": sum(busy.values())}
+        # durations of the same dispatches from the counter run's own kernel trace
+        md_durs = [int(x["End_Timestamp"]) - int(x["Start_Timestamp"])
+                   for x in _csv_rows(a.mfma, "kernel_trace.csv") if a.kernel in x["Kernel_Name"]]
+        if md_durs and len(md_durs) == len(inst):
+            tf = n_inst * fpi / (sum(md_durs) * 1e-9) / 1e12
+            mc.update(duration_ms_total=sum(md_durs) / 1e6, executed_tflops_from_counters=tf,
+                      frac_of_peak_from_counters=tf / peak)
+        rec["mfma_counters"] = mc
+    md += ["## Figures", "",
+           f"* {a.kernel}: {launches} launches per batch, average {avg_ms:.3f} ms per launch "
+           f"({len(durs)} launches traced); algorithmic flops per launch (8 per complex MAC) "
+           f"{flops_l:.4e} -> {alg_tf:.1f} TFLOP/s algorithmic, {exe_tf:.1f} TFLOP/s executed on the "
+           f"matrix cores = {100 * exe_tf / peak:.1f} % of the {peak} TFLOP/s dense peak.",
+           f"* HBM traffic per launch: fetch {fetch_l:.4e} B + write {write_l:.4e} B = "
+           f"{fetch_l + write_l:.4e} B against {bytes_l:.4e} B algorithmic (A + B + C once) = "
+           f"{(fetch_l + write_l) / bytes_l:.2f} x.",
+           f"* Counter scale from a {a.copy_mib} MiB device copy (`{cfn[kf][:60]}`): FETCH_SIZE x "
+           f"{fetch_scale:.4f}, WRITE_SIZE x {write_scale:.4f}.",
+           f"* k_mfma.hip sha256 at measurement: `{rec['source_sha256']}`"]
+    if "mfma_counters" in rec and "executed_tflops_from_counters" in rec["mfma_counters"]:
+        mc = rec["mfma_counters"]
+        md.append(f"* MFMA instruction counters: {mc['mfma_instructions']:.4e} instructions x "
+                  f"{mc['flops_per_instruction']} flops in {mc['duration_ms_total']:.1f} ms of kernel time "
+                  f"({mc['dispatches']} dispatches; counter runs serialise kernels) = "
+                  f"{mc['executed_tflops_from_counters']:.1f} TFLOP/s = "
+                  f"{100 * mc['frac_of_peak_from_counters']:.1f} % of peak.")
+    md.append("")
+    stats = _csv_rows(a.trace, "kernel_stats.csv")
+    if stats:
+        md += ["## Kernel statistics (`--kernel-trace --stats`)", "",
+               "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+        for x in stats[:20]:
+            g = lambda *ks: next((x[k] for k in ks if k in x), "0")
+            md.append(f"| {g('Name', 'KernelName')[:90]} | {g('Calls')} | "
+                      f"{float(g('TotalDurationNs')) / 1e6:.3f} | {float(g('AverageNs')) / 1e3:.1f} | "
+                      f"{float(g('Percentage')):.2f} |")
+        md.append("")
+    json.dump(rec, open(a.out + ".json", "w"), indent=1)
+    open(a.out + ".md", "w").write("\n".join(md) + "\n")
+    print(json.dumps(rec))
 
 
 def main():
@@ -117,22 +538,22 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rqc53", choices=["rqc53", "rqc30"],
+                    help="headline workload: rqc53 walks the seeded 1024-slice subset one batch "
+                         "per step; rqc30 runs every slice per step")
     ap.add_argument("--modes", default="c64,split_f16,split_bf16",
                     help="comma list; the first is the headline value, the others are reported beside it")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--tune-cache", default=None, help="autotuner cache (JSON, keyed by mode and step shape)")
-    ap.add_argument("--workload", default="rqc30", choices=["rqc30", "rqc53"],
-                    help="rqc30: every slice per step; rqc53: a seeded sample of --slices slices")
-    ap.add_argument("--slices", type=int, default=8, help="rqc53: sampled slices per step")
-    ap.add_argument("--path", default="greedy", choices=["greedy", "reconf"],
-                    help="path of the headline plan: randomised greedy (the workload's definition) "
-                         "or greedy + subtree reconfiguration")
-    ap.add_argument("--reconf-k", type=int, default=None,
-                    help="subtree reconfiguration window (default: 10 for rqc30, 8 for rqc53)")
+    ap.add_argument("--extras", default="rqc30,grad",
+                    help="comma list of extra legs: rqc30 (30-qubit workload), grad (20-qubit "
+                         "gradient); '' for none")
+    ap.add_argument("--rqc30-modes", default="c64,split_f16,split_bf16")
     ap.add_argument("--path-variant", default="c64,split_bf16",
-                    help="modes to time on the reconfigured path as well ('' to skip)")
-    ap.add_argument("--no-grad", action="store_true",
-                    help="skip the gradient leg (20-qubit, 720 angles, 256 bitstrings)")
+                    help="rqc30 modes to time on the reconfigured path as well ('' to skip)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
+    ap.add_argument("--no-golden", action="store_true",
+                    help="skip the error checks on stored oracle slices (profiled runs: they launch "
+                         "one-slice batches)")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache (JSON, keyed by mode and step shape)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -157,198 +578,86 @@ def main():
     from workload import make_workload
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    from workload import sample_slice_ids
-    w = make_workload(args.workload)
-    ref = np.load(GOLDEN) if os.path.exists(GOLDEN) else None
+    extras = [e for e in args.extras.split(",") if e]
+    modes = args.modes.split(",")
+    main_mode = modes[0]
 
-    def run_plan(pr, mode_list, tag, fuse_rank=0):
-        """Bind a prepared plan and time each mode on it; returns (results,
-        plan facts)."""
+    if args.workload == "rqc53":
+        w = make_workload("rqc53")
         t0 = time.perf_counter()
-        plan = pr.plan(fuse_rank=fuse_rank)
-        costs = P.tree_costs(pr.net, pr.path, pr.sliced)
-        t_plan = time.perf_counter() - t0 + pr_seconds[tag]
-        if args.workload == "rqc30":
-            n_slices = 1 << len(pr.sliced)
-            ids = None
-        else:
-            # the seeded subset of 2^10 slice ids, first --slices of them
-            ids = sample_slice_ids(len(pr.sliced), 1024, 3)[: args.slices]
-            n_slices = len(ids)
-        info = plan.info()
-        macs_slice = info["macs_per_slice"]
-        flops_step = 8.0 * macs_slice * n_slices
-        steps = plan.steps()
-        log(f"[{tag}] planned in {t_plan:.2f}s: |S|={len(pr.sliced)} C(B,S)=2^{costs.log2_sliced:.2f} "
-            f"overhead={costs.overhead:.4f} per-slice MACs={macs_slice:.3e}")
-        batch = plan.bind(batch=n_slices) if plan.workspace_size(n_slices) < 0.7 * torch.cuda.mem_get_info()[0] \
-            else plan.bind()
-        log(f"[{tag}] bound: batch={batch}, workspace={plan.workspace_size(batch) / 2**30:.2f} GiB")
-
-        def run_step(out, mode):
-            if ids is None:
-                plan.execute_range(0, n_slices, out, mode)
-            else:
-                plan.execute(ids, out, mode)
-
-        def measure(mode):
-            t0 = time.perf_counter()
-            cache = args.tune_cache  # one file for all modes (keys carry the mode)
-            plan.autotune(mode, cache)
-            log(f"[{tag}/{mode}] autotuned in {time.perf_counter() - t0:.2f}s")
-            out = plan.new_output()
-            for _ in range(args.warmup):
-                out.zero_()
-                run_step(out, mode)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                out.zero_()
-                run_step(out, mode)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            res = {"tflops": flops_step * args.steps / dt / 1e12, "ms_per_step": 1e3 * dt / args.steps,
-                   "sec_per_slice": dt / args.steps / n_slices}
-            if ref is not None and args.workload == "rqc30":
-                got = out.cpu().numpy()
-                res["rel_l2_error"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-            # the dominant kernel (the MFMA complex GEMM): live per-step HIP
-            # events on the plan's stream (a replay of one batch outside the graph)
-            ms = np.zeros(len(steps))
-            reps = 3
-            for _ in range(reps):
-                ms += plan.profile_steps(0 if ids is None else int(ids[0]), mode)
-            ms /= reps
-            mf_flops, mf_ms, mf_launch, split_flops = 0.0, 0.0, 0, 0.0
-            for k, st in enumerate(steps):
-                kind, _, _, _ = plan.step_kernel(k, mode)
-                if kind in (1, 2):
-                    f = 8.0 * (1 << (st["m"] + st["k"] + st["n"])) * batch
-                    mf_flops += f
-                    mf_ms += ms[k]
-                    mf_launch += 1
-                    if kind == 2:
-                        split_flops += f
-            res["mfma_ms_per_batch"] = mf_ms
-            res["step_ms_per_batch"] = float(ms.sum())
-            res["mfma_launches_per_batch"] = mf_launch
-            res["mfma_tflops"] = mf_flops / (mf_ms * 1e-3) / 1e12 if mf_ms > 0 else 0.0
-            res["split_mac_fraction"] = split_flops / (8.0 * macs_slice * batch)
-            log(f"[{tag}/{mode}] {res['ms_per_step']:.2f} ms/step, {res['tflops']:.2f} TFLOP/s, "
-                f"MFMA {mf_ms:.2f} of {res['step_ms_per_batch']:.2f} ms per batch "
-                f"({res['mfma_tflops']:.2f} TFLOP/s), err {res.get('rel_l2_error')}")
-            return res
-
-        results = {m: measure(m) for m in mode_list}
-        facts = dict(n_slices=n_slices, batch=batch, costs=costs, macs_slice=macs_slice,
-                     flops_step=flops_step, n_sliced=len(pr.sliced), plan_seconds=t_plan,
-                     groups=plan.groups())
-        del plan
-        torch.cuda.empty_cache()
-        return results, facts
-
-    pr_seconds = {}
-    reconf_k = args.reconf_k if args.reconf_k is not None else (10 if args.workload == "rqc30" else 8)
-    t0 = time.perf_counter()
-    pr = P.prepare(w, reconf_k=reconf_k if args.path == "reconf" else 0)
-    pr_seconds[args.path] = time.perf_counter() - t0
-    results, facts = run_plan(pr, args.modes.split(","), args.path)
-    n_slices, batch, costs = facts["n_slices"], facts["batch"], facts["costs"]
-    macs_slice, flops_step = facts["macs_slice"], facts["flops_step"]
-
-    # the same workload on a better path: greedy trials improved by subtree
-    # reconfiguration
-    variant = None
-    if args.path_variant and args.path == "greedy":
-        t0 = time.perf_counter()
-        prv = P.prepare(w, reconf_k=reconf_k)
-        pr_seconds["reconf"] = time.perf_counter() - t0
-        vres, vf = run_plan(prv, args.path_variant.split(","), "reconf")
-        variant = {"path": f"randomised greedy + subtree reconfiguration (k={reconf_k})",
-                   "plan_seconds": round(vf["plan_seconds"], 3),
-                   "sliced_indices": vf["n_sliced"], "log2_C_BS": round(vf["costs"].log2_sliced, 4),
-                   "overhead": round(vf["costs"].overhead, 5), "macs_per_slice": vf["macs_slice"],
-                   "projected_seconds_all_slices": {m: r["sec_per_slice"] * 2.0 ** vf["n_sliced"]
-                                                    for m, r in vres.items()},
-                   "modes": {m: {k: sig6(v) for k, v in r.items()} for m, r in vres.items()}}
-        if args.workload == "rqc30":
-            # the same path with fused sub-paths (secondary slicing, working rank 10)
-            pr_seconds["reconf+fused"] = pr_seconds["reconf"]
-            fres, ff = run_plan(prv, ["c64"], "reconf+fused", fuse_rank=10)
-            variant["fused_sub_paths"] = {
-                "fuse_rank": 10, "groups": len(ff["groups"]),
-                "steps_fused": sum(g["n_steps"] for g in ff["groups"]),
-                "c64": {k: sig6(v) for k, v in fres["c64"].items()}}
-        for m, r in vres.items():
-            if m in results:
-                variant["modes"][m]["time_to_solution_speedup_vs_greedy_path"] = round(
-                    (results[m]["sec_per_slice"] * 2.0 ** len(pr.sliced)) /
-                    (r["sec_per_slice"] * 2.0 ** vf["n_sliced"]), 3)
-
-    main_mode = args.modes.split(",")[0]
-    r0 = results[main_mode]
-    tflops, ms_step, err = r0["tflops"], r0["ms_per_step"], r0.get("rel_l2_error")
-    if main_mode == "c64":
-        peak, achieved = PEAK_FP32_MFMA_TFLOPS, r0["mfma_tflops"]
+        pr = P.prepare(w)
+        t_plan = time.perf_counter() - t0
+        log(f"[rqc53] host planner (randomised greedy search + Algorithm 1) {t_plan:.2f}s")
+        golden, meta = rqc53_golden() if not args.no_golden else (None, None)
+        if meta is not None and meta["sliced"] != pr.sliced:
+            log("[rqc53] the stored oracle slices belong to another slicing set; no error reported")
+            golden = None
+        results, f = time_plan(torch, P, pr, "rqc53", modes, args, "rqc53", golden=golden)
+        walked = f["per_step"] * args.steps
+        wl = (f"{WORKLOAD_TEXT['rqc53']}, randomised greedy path, |S|={f['n_sliced']}; one step = one "
+              f"batch of {f['per_step']} slices walking the seeded subset of 1024 slice ids "
+              f"(seed 3); {walked} slices timed")
     else:
-        # split: three fp16/bf16 matrix products per real product; executed
-        # matrix flops are 3x the algorithmic count
-        peak, achieved = PEAK_F16_MFMA_TFLOPS, 3.0 * r0["mfma_tflops"]
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": counter_traffic(main_mode),
-                "kernel": "k_cgemm_c64" if main_mode == "c64" else "k_cgemm_split",
-                "launches_per_batch": r0["mfma_launches_per_batch"],
-                "share_of_step_time": round(r0["mfma_ms_per_batch"] / r0["step_ms_per_batch"], 4)}
-    modes = {}
-    for m, r in results.items():
-        modes[m] = {k: sig6(v) for k, v in r.items()}
-        modes[m]["speedup_vs_c64"] = round(r["tflops"] / results["c64"]["tflops"], 4) if "c64" in results else None
-        modes[m]["meets_tolerance"] = (r.get("rel_l2_error") is not None and
-                                       r["rel_l2_error"] <= (1e-4 if m == "c64" else 5e-4))
-
-    grad = None
-    if not args.no_grad and args.workload == "rqc30":
-        grad = gradient_leg(torch, P, args)
-
-    cpu = None
-    if not args.no_cpu and args.workload == "rqc30":
-        log("timing the CPU oracle on one slice ...")
-        cpu = cpu_baseline()
-        log(f"oracle: {cpu['sec_per_slice']:.2f} s/slice, {cpu['value']:.4f} TFLOP/s on "
-            f"{cpu['cores']} threads")
-
+        w = make_workload("rqc30")
+        t0 = time.perf_counter()
+        pr = P.prepare(w)
+        t_plan = time.perf_counter() - t0
+        ref_path = os.path.join(GOLDEN, "rqc30_amplitudes.npy")
+        golden = {"amplitudes": np.load(ref_path)} if os.path.exists(ref_path) and not args.no_golden else None
+        results, f = time_plan(torch, P, pr, "rqc30", modes, args, "rqc30", golden=golden)
+        wl = WORKLOAD_TEXT["rqc30"] + ", all slices per step, randomised greedy path"
+        extras = [e for e in extras if e != "rqc30"]
+    r0 = results[main_mode]
+    n_sliced = f["n_sliced"]
     line = {
         "metric": "contraction TFLOP/s + sec/slice on 1 GPU; split-FP16 vs complex64 at stated error",
-        "value": round(tflops, 3),
+        "value": round(r0["tflops"], 3),
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 3),
+        "ms_per_step": round(r0["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"c64": "c64", "split_f16": "f16x2", "split_bf16": "bf16x2"}[main_mode],
         "data": "synthetic",
-        "config": {"workload": ("rqc30: 5x6 grid, 14 cycles, 6 open qubits (64 amplitudes), "
-                                "max rank 26, all slices per step") if args.workload == "rqc30" else
-                               (f"rqc53: 6x9 grid minus one site, 20 cycles, 20 open qubits (2^20 "
-                                f"amplitudes), max rank 30, {n_slices} seeded slices per step"),
-                   "projected_seconds_all_slices": r0["sec_per_slice"] * 2.0 ** len(pr.sliced),
-                   "slices": n_slices, "sliced_indices": len(pr.sliced), "batch": batch,
-                   "log2_C_BS": round(costs.log2_sliced, 4), "overhead": round(costs.overhead, 5),
-                   "macs_per_slice": macs_slice, "flops_per_step": flops_step,
-                   "mode": main_mode, "path": args.path},
+        "config": {"workload": wl, "mode": main_mode, "path": "randomised greedy",
+                   "slices_per_step": f["per_step"], "batch": f["batch"], "sliced_indices": n_sliced,
+                   "log2_C_BS": round(f["costs"].log2_sliced, 4), "overhead": round(f["costs"].overhead, 5),
+                   "macs_per_slice": f["macs_slice"], "flops_per_step": f["flops_step"],
+                   "plan_seconds": round(t_plan, 3)},
         "sec_per_slice": r0["sec_per_slice"],
-        "rel_l2_error": err,
-        "modes": modes,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "path_variant": variant,
-        "gradient": grad,
+        "projection": {"slices": float(2.0 ** n_sliced),
+                       "seconds_all_slices": {m: r["sec_per_slice"] * 2.0 ** n_sliced for m, r in results.items()},
+                       "total_flops_8C_BS": 8.0 * f["costs"].sliced},
+        "rel_l2_error": r0.get("rel_l2_error"),
+        "modes": mode_table(results),
+        "roofline": roofline_of(args.workload, main_mode, r0),
+        "cpu_baseline": None,
     }
+    if "rqc30" in extras:
+        line["rqc30"] = rqc30_extra(torch, P, args)
+    if "grad" in extras:
+        line["gradient"] = gradient_leg(torch, P, args)
+    if not args.no_cpu:
+        log("timing the CPU oracle ...")
+        if args.workload == "rqc53":
+            line["cpu_baseline"] = cpu_rqc53(pr.sliced)
+        else:
+            line["cpu_baseline"] = cpu_rqc30()
+        if line["cpu_baseline"] is not None:
+            cb = line["cpu_baseline"]
+            log(f"oracle: {cb['sec_per_slice']:.2f} s/slice, {cb['value']:.4f} TFLOP/s on {cb['cores']} cores")
+        if "rqc30" in line:
+            line["rqc30"]["cpu_baseline"] = cpu_rqc30()
+        if "gradient" in line:
+            line["gradient"]["cpu_baseline"] = cpu_gradient()
     print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "summarize":
+        summarize_main(sys.argv[2:])
+    else:
+        main()
