@@ -337,6 +337,7 @@ def test_rqc53_reconfigured_sampled_slice(torch):
     banner("rqc53 reconfigured plan")
     pr = P.prepare(w, reconf_k=8)
     assert pr.sliced == meta["sliced"]
+    assert len(meta["slices"]) >= 2
     plan = pr.plan()
     plan.bind(batch=1)
     for j, rec in enumerate(meta["slices"]):
