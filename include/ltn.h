@@ -487,7 +487,10 @@ ltn_status ltn_permute(const void* d_in, void* d_out, int32_t rank, const int32_
  * n <= 6: A tile in LDS, B broadcast from LDS, outputs staged in address
  * order), 4 = split-sum kernel for steps with few outputs (m <= 3, n <= 3:
  * the sum over k is cut into chunks reduced by separate blocks, FP32
- * partials added in FP32 in a fixed order); cfg = tile configuration of that
+ * partials added in FP32 in a fixed order), 5 = split-K complex64 MFMA GEMM
+ * (sums of 2^10 and more cut into chunks that separate blocks reduce on the
+ * matrix cores, tiles down to 16 complex columns, FP32 partials added in
+ * chunk order by a second pass); cfg = tile configuration of that
  * kind (-1 for the generic kernel); swap = operands exchanged (rows come
  * from B). Requires a bound plan. */
 /* Force the kernel of one step in one mode (same encoding as

@@ -133,11 +133,13 @@ __device__ __forceinline__ float split_out_scale(const GemmDesc& d, int64_t b, i
   return scale_of(__float_as_uint(bound));
 }
 
-template <int BM, int BNC, int BKC>
+// NWN waves along the columns (2: waves 2 x 2; 1: waves 4 x 1, for tiles
+// of 16 complex columns)
+template <int BM, int BNC, int BKC, int NWN = 2>
 struct Cfg {
-  static constexpr int WM = BM / 2;          // rows per wave
+  static constexpr int WM = BM / (4 / NWN);  // rows per wave
   static constexpr int TM = WM / 32;         // 32-row MFMA tiles per wave
-  static constexpr int WNC = BNC / 2;        // complex columns per wave
+  static constexpr int WNC = BNC / NWN;      // complex columns per wave
   static constexpr int TN = (2 * WNC) / 32;  // 32-real-column MFMA tiles per wave
   static constexpr int LDA = BKC + 1;        // padded row length (complex)
   static constexpr int CHA = BM * BKC / 2;   // float4 chunks of the A tile
@@ -147,24 +149,36 @@ struct Cfg {
   static_assert(TM >= 1 && TN >= 1 && BKC >= 2, "tile too small");
 };
 
-template <int BM, int BNC, int BKC>
+// SPLITK: block w takes chunk w / (tiles * nb) of the sum (2^kc_bits
+// consecutive k) for tile w % (tiles * nb), and writes its FP32 partial of
+// C to part in plain row-major order ([b][chunk][row][column]); the split
+// layout and the per-slice maxima are left to the pass that adds the chunks.
+template <int BM, int BNC, int BKC, int NWN = 2, bool SPLITK = false>
 __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
-  using C = Cfg<BM, BNC, BKC>;
+  using C = Cfg<BM, BNC, BKC, NWN>;
   __shared__ float2 As[BM * C::LDA];
   __shared__ float2 Bs[BNC * C::LDA];
 
   const int64_t M = int64_t(1) << d.m, N = int64_t(1) << d.n, K = int64_t(1) << d.k;
-  int64_t b, bm, bn;
-  tile_of(blockIdx.x, M / BM, N / BNC, d.nb, b, bm, bn);
+  int64_t b, bm, bn, chunk = 0, w = blockIdx.x;
+  if constexpr (SPLITK) {
+    const int64_t per = (M / BM) * (N / BNC) * d.nb;
+    chunk = w / per;
+    w -= chunk * per;
+  }
+  tile_of(w, M / BM, N / BNC, d.nb, b, bm, bn);
+  const int64_t KL = SPLITK ? (int64_t(1) << d.kc_bits) : K;  // sum length of this block
+  const int64_t k_first = chunk * KL;
 
-  const float2* A = d.A + b * d.sA + bm * BM * K;
-  const float2* B = d.B + b * d.sB + bn * BNC * K;
-  float* Cf = reinterpret_cast<float*>(d.C + b * d.sC);
-  const float so = d.split_out == 2 ? split_out_scale(d, b, K, bm == 0 && bn == 0 && threadIdx.x == 0) : 1.f;
+  const float2* A = d.A + b * d.sA + bm * BM * K + k_first;
+  const float2* B = d.B + b * d.sB + bn * BNC * K + k_first;
+  float* Cf = SPLITK ? reinterpret_cast<float*>(d.part + ((b << (d.k - d.kc_bits)) + chunk) * (M * N))
+                     : reinterpret_cast<float*>(d.C + b * d.sC);
+  const float so = !SPLITK && d.split_out == 2 ? split_out_scale(d, b, K, bm == 0 && bn == 0 && threadIdx.x == 0) : 1.f;
   uint32_t* Cw = reinterpret_cast<uint32_t*>(d.C + b * d.sC);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / NWN, wn = wave % NWN;
   const int h = lane >> 5, i = lane & 31;
 
   floatx16 acc[C::TM][C::TN];
@@ -222,11 +236,11 @@ __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
   const bool im_col = (i & 1) != 0;
 
   load(0);
-  for (int64_t k0 = 0; k0 < K; k0 += BKC) {
+  for (int64_t k0 = 0; k0 < KL; k0 += BKC) {
     __syncthreads();
     stash();
     __syncthreads();
-    if (k0 + BKC < K) load(k0 + BKC);
+    if (k0 + BKC < KL) load(k0 + BKC);
 #pragma unroll
     for (int kp = 0; kp < BKC; kp += 2) {
       float2 av[C::TM], bv[C::TN];
@@ -248,8 +262,9 @@ __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
   }
 
   // epilogue: pdep is additive over disjoint bit groups of the row index
-  const uint64_t maskA = d.cmask;
-  const uint64_t maskB = ~d.cmask & ((1ull << (d.m + d.n)) - 1);
+  // (split-K partials: plain row-major, the row bits above the column bits)
+  const uint64_t maskA = SPLITK ? ((uint64_t)(M - 1) << d.n) : d.cmask;
+  const uint64_t maskB = ~maskA & ((1ull << (d.m + d.n)) - 1);
   const uint64_t row_base = (uint64_t)(bm * BM + wm * C::WM + 4 * h);
   const uint64_t pbase = pdep64(row_base, maskA);
   uint64_t pq[4], pg[4], pt[C::TM];
@@ -273,7 +288,7 @@ __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
           uint64_t addr = pbase | pt[x] | pg[g] | pq[q] | pn;
           float v = acc[x][y][4 * g + q];
           vmax = fmaxf(vmax, fabsf(v));
-          if (d.split_out) {
+          if (!SPLITK && d.split_out) {
             // re and im of this output sit on neighbouring lanes: the even
             // lane writes the hi word, the odd lane the lo word
             const float o = __shfl_xor(v, 1, 64);
@@ -289,7 +304,28 @@ __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
           }
         }
   }
-  if (d.scale_c) record_max(d.scale_c + b, vmax);
+  if (!SPLITK && d.scale_c) record_max(d.scale_c + b, vmax);
+}
+
+// Second pass of the split-K GEMM: C[b][merge(row, column)] = the chunks'
+// partials added in FP32 in chunk order. One thread per output; 2^(m+n) is
+// a multiple of the block size, so a block (and a wave) stays in one slice.
+__global__ __launch_bounds__(256) void k_splitk_reduce(GemmDesc d) {
+  const int64_t MN = int64_t(1) << (d.m + d.n);
+  const int chunks = 1 << (d.k - d.kc_bits);
+  const uint64_t full = (1ull << (d.m + d.n)) - 1;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t b = i >> (d.m + d.n), e = i & (MN - 1);
+  const float2* src = d.part + (b * chunks) * MN + e;
+  float re = 0.f, im = 0.f;
+  for (int c = 0; c < chunks; ++c) {
+    const float2 v = src[c * MN];
+    re += v.x;
+    im += v.y;
+  }
+  const uint64_t row = (uint64_t)e >> d.n, col = (uint64_t)e & ((1ull << d.n) - 1);
+  d.C[b * d.sC + (pdep64(row, d.cmask) | pdep64(col, ~d.cmask & full))] = make_float2(re, im);
+  if (d.scale_c) record_max(d.scale_c + b, fmaxf(fabsf(re), fabsf(im)));
 }
 
 
@@ -641,6 +677,28 @@ void run(const GemmDesc& d, hipStream_t st) {
   hipLaunchKernelGGL((k_cgemm_c64<BM, BNC, BKC>), dim3((unsigned)tiles), dim3(256), 0, st, d);
 }
 
+// Split-K tiles: waves 4 x 1 for 16 and 32 complex columns, 2 x 2 otherwise.
+struct SplitKCfg {
+  int bm, bnc, bkc;
+  const char* name;
+};
+const SplitKCfg kSplitKCfgs[] = {
+    {128, 16, 16, "splitk_128x16x16"},
+    {256, 16, 16, "splitk_256x16x16"},
+    {128, 32, 16, "splitk_128x32x16"},
+    {128, 64, 16, "splitk_128x64x16"},
+};
+constexpr int kNumSplitK = sizeof(kSplitKCfgs) / sizeof(kSplitKCfgs[0]);
+
+template <int BM, int BNC, int BKC, int NWN>
+void run_splitk(const GemmDesc& d, hipStream_t st) {
+  const int64_t chunks = int64_t(1) << (d.k - d.kc_bits);
+  const int64_t blocks = ((int64_t(1) << d.m) / BM) * ((int64_t(1) << d.n) / BNC) * d.nb * chunks;
+  hipLaunchKernelGGL((k_cgemm_c64<BM, BNC, BKC, NWN, true>), dim3((unsigned)blocks), dim3(256), 0, st, d);
+  const int64_t outs = (int64_t(1) << (d.m + d.n)) * d.nb;
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)(outs / 256)), dim3(256), 0, st, d);
+}
+
 template <int BM, int BNC, int BKC, bool DMA = false, int NWN = 2>
 void run_split(const GemmDesc& d, bool bf, hipStream_t st) {
   int64_t tiles = ((int64_t(1) << d.m) / BM) * ((int64_t(1) << d.n) / BNC) * d.nb;
@@ -664,6 +722,44 @@ bool gemm_config_fits(int cfg, int m, int k, int n, int mode) {
 
 const char* gemm_config_name(int cfg, int mode) {
   return cfg >= 0 && cfg < gemm_config_count(mode) ? info_of(cfg, mode).name : "?";
+}
+
+// About 2^12 (tile, chunk) pairs per slice for a 128 x 16 tile, each chunk
+// at least 2^8 long; offered only for sums of 2^10 and more.
+int splitk_chunk_bits(int m, int k, int n) {
+  if (k < 10 || m >= 40 || n >= 40) return 0;
+  int c = 23 - (m + n);
+  if (c > k - 8) c = k - 8;
+  return c > 0 ? c : 0;
+}
+
+int splitk_config_count() { return kNumSplitK; }
+
+bool splitk_config_fits(int cfg, int m, int k, int n) {
+  if (cfg < 0 || cfg >= kNumSplitK) return false;
+  const int c = splitk_chunk_bits(m, k, n);
+  const SplitKCfg& t = kSplitKCfgs[cfg];
+  return c > 0 && (1ll << m) >= t.bm && (1ll << n) >= t.bnc && (1ll << (k - c)) >= t.bkc;
+}
+
+const char* splitk_config_name(int cfg) { return cfg >= 0 && cfg < kNumSplitK ? kSplitKCfgs[cfg].name : "?"; }
+
+int64_t splitk_part_elems(int m, int k, int n) {
+  for (int c = 0; c < kNumSplitK; ++c)
+    if (splitk_config_fits(c, m, k, n) || splitk_config_fits(c, n, k, m))
+      return (int64_t(1) << splitk_chunk_bits(m, k, n)) << (m + n);
+  return 0;
+}
+
+void launch_cgemm_splitk(const GemmDesc& d0, hipStream_t st) {
+  GemmDesc d = d0;
+  d.kc_bits = d.k - splitk_chunk_bits(d.m, d.k, d.n);
+  switch (d.cfg) {
+    case 0: run_splitk<128, 16, 16, 1>(d, st); break;
+    case 1: run_splitk<256, 16, 16, 1>(d, st); break;
+    case 2: run_splitk<128, 32, 16, 1>(d, st); break;
+    case 3: run_splitk<128, 64, 16, 2>(d, st); break;
+  }
 }
 
 void launch_split_convert(const float2* X, float2* Y, int rank, int nb, const uint32_t* slot,

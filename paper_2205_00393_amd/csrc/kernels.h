@@ -99,6 +99,8 @@ struct GemmDesc {
   const uint32_t* max_a;     // split_out 2: recorded max |Re|, |Im| of A and of B,
   const uint32_t* max_b;     //   whose bound 2 K max_a max_b sets C's fp16 scale
   uint32_t* bound_c;         //   and is stored here per slice for the consumer
+  float2* part;              // split-K: [nb][chunks][2^(m+n)] FP32 partial sums
+  int32_t kc_bits;           // split-K: log2 of the sum length of one chunk
 };
 // Tile plan of a bit permutation (built on the host by ltn_permute).
 struct PermuteDesc {
@@ -176,6 +178,16 @@ int gemm_config_count(int mode);
 bool gemm_config_fits(int cfg, int m, int k, int n, int mode);
 const char* gemm_config_name(int cfg, int mode);
 void launch_cgemm(const GemmDesc& d, int mode, hipStream_t st);
+// Split-K complex64 MFMA GEMM for steps with a long sum and few outputs
+// per slice (tiles down to 16 complex columns): blocks take a tile and one
+// chunk of the sum and write FP32 partials; a second pass adds the chunks
+// in a fixed order and writes C (and its per-slice max when scale_c is set).
+int splitk_config_count();
+bool splitk_config_fits(int cfg, int m, int k, int n);
+const char* splitk_config_name(int cfg);
+int splitk_chunk_bits(int m, int k, int n);  // log2 of the number of chunks (0: not offered)
+int64_t splitk_part_elems(int m, int k, int n);  // partial elements per slice
+void launch_cgemm_splitk(const GemmDesc& d, hipStream_t st);
 // complex64 tensor X (2^rank per slice, rank >= 2) -> its split-layout
 // copy Y in the given split mode (fp16 scaled by the per-slice max slot[b]).
 void launch_split_convert(const float2* X, float2* Y, int rank, int nb, const uint32_t* slot,

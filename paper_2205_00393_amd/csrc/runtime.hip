@@ -28,7 +28,7 @@ using namespace ltn;
 
 struct Layout {
   size_t leafdata, gd_fwd, gd_grad, gd_gcot, pl, angles, leafgrad, ids, scales, arena, split, gscr,
-      gscr_c, skinny, gdesc, fdesc, total;
+      gscr_c, skinny, splitk, gdesc, fdesc, total;
 };
 
 struct ltn_plan_impl {
@@ -48,7 +48,8 @@ struct ltn_plan_impl {
   // kernel choice per mode and step: kind 0 = generic (tk threads per
   // output), 1 = complex64 MFMA GEMM, 2 = split MFMA GEMM (cfg, swap),
   // 3 = narrow-step kernel (swap: rows taken from the B operand), 4 = split
-  // sum over k for steps with few outputs
+  // sum over k for steps with few outputs, 5 = split-K complex64 MFMA GEMM
+  // (cfg, swap) for long sums with too few columns for a full tile
   struct Choice {
     int kind = 0, cfg = -1, swap = 0, tk = 1;
   };
@@ -124,6 +125,11 @@ Layout layout(const ltn_plan* p, int B, int grad) {
     if (skinny_fits(sp.m, sp.k, sp.n)) sk = std::max<int64_t>(sk, skinny_part_elems(sp.m, sp.k, sp.n));
   l.skinny = o;
   o = al(o + (size_t)B * (size_t)sk * 8);
+  // split-K partials (largest over the steps a split-K tile fits)
+  int64_t kp = 0;
+  for (auto& sp : p->steps) kp = std::max<int64_t>(kp, splitk_part_elems(sp.m, sp.k, sp.n));
+  l.splitk = o;
+  o = al(o + (size_t)B * (size_t)kp * 8);
   l.gdesc = o;  // gradient runs: at most one descriptor per step forward, two backward
   if (grad) o = al(o + 3 * p->steps.size() * sizeof(GenericDesc));
   l.fdesc = o;  // forward runs: one descriptor per step and mode
@@ -237,6 +243,26 @@ void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena, int mode) {
     d.part = reinterpret_cast<float2*>(r.ws + r.lay.skinny);
     if (mode == LTN_SPLIT_F16) d.scale_c = slot(p, sp.out);
     launch_skinny(d, r.st);
+    return;
+  }
+  if (ch.kind == 5) {
+    GemmDesc d{};
+    const bool sw = ch.swap;
+    d.A = sw ? B : A;
+    d.B = sw ? A : B;
+    d.C = C;
+    d.sA = int64_t(1) << (sw ? tb.rank : ta.rank);
+    d.sB = int64_t(1) << (sw ? ta.rank : tb.rank);
+    d.sC = int64_t(1) << tc.rank;
+    d.m = sw ? sp.n : sp.m;
+    d.n = sw ? sp.m : sp.n;
+    d.k = sp.k;
+    d.cmask = sw ? (~cm & full) : cm;
+    d.nb = nb;
+    d.cfg = ch.cfg;
+    d.part = reinterpret_cast<float2*>(r.ws + r.lay.splitk);
+    if (mode == LTN_SPLIT_F16) d.scale_c = slot(p, sp.out);
+    launch_cgemm_splitk(d, r.st);
     return;
   }
   if (ch.kind == 3) {
@@ -652,6 +678,16 @@ void bind_state(ltn_plan* p, ltn_plan_impl* r, char* d_ws, size_t bytes, int gra
             }
           }
         }
+      }
+      // no full tile but a long sum: the split-K tile (the small side as columns)
+      if (ch.kind == 0) {
+        const bool sw = sp.n > sp.m;
+        for (int c = 0; c < splitk_config_count() && ch.kind == 0; ++c)
+          if (sw ? splitk_config_fits(c, sp.n, sp.k, sp.m) : splitk_config_fits(c, sp.m, sp.k, sp.n)) {
+            ch.kind = 5;
+            ch.cfg = c;
+            ch.swap = sw;
+          }
       }
       // few outputs and a long sum: split the sum over blocks
       if (ch.kind == 0 && skinny_fits(sp.m, sp.k, sp.n) && sp.k >= 10) {
@@ -1312,6 +1348,15 @@ extern "C" ltn_status ltn_autotune(ltn_plan* p, int32_t mode, const char* cache_
           ch.cfg = 0;
           cands.push_back(ch);
         }
+        for (int sw = 0; sw < 2; ++sw)
+          for (int c = 0; c < splitk_config_count(); ++c)
+            if (sw ? splitk_config_fits(c, sp.n, sp.k, sp.m) : splitk_config_fits(c, sp.m, sp.k, sp.n)) {
+              Choice ch;
+              ch.kind = 5;
+              ch.cfg = c;
+              ch.swap = sw;
+              cands.push_back(ch);
+            }
         // the generic kernel only competes on small steps (or when no tile fits)
         if (cands.empty() || (cands.size() == 1 && cands[0].kind == 4) || sp.m + sp.k + sp.n <= 22)
           for (int tk : {1, 8, 64})
@@ -1419,6 +1464,11 @@ extern "C" ltn_status ltn_set_step_kernel(ltn_plan* p, int32_t step, int32_t mod
       require(skinny_fits(sp.m, sp.k, sp.n), "the split-sum kernel needs m <= 3 and n <= 3");
       c.kind = 4;
       c.cfg = 0;
+    } else if (kind == 5) {
+      require(splitk_config_fits(cfg, m, sp.k, n), "split-K tile configuration does not fit the step");
+      c.kind = 5;
+      c.cfg = cfg;
+      c.swap = swap ? 1 : 0;
     } else {
       require(false, "unknown kernel kind");
     }

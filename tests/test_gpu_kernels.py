@@ -2,7 +2,9 @@
 ltn_set_step_kernel: narrow-step kernel in both operand roles, generic
 kernel with 1, 8 and 64 threads per output, complex64 MFMA tiles, and the
 split tiles (register- and DMA-staged) in the split modes. Each forced plan must reproduce the
-brute-force state-vector amplitudes (complex64 <= 1e-4, split <= 5e-4)."""
+brute-force state-vector amplitudes (complex64 <= 1e-4, split <= 5e-4).
+The split-sum and split-K kernels, whose steps the reduced circuits do
+not have, run alone on one-step networks against the exact product."""
 import numpy as np
 import pytest
 
@@ -177,3 +179,36 @@ def test_split_sum_single_step(torch, m, k, n):
         err = rel_l2(out.cpu().numpy(), exact)
         banner(f"split sum ({m},{k},{n}) {mode}: rel err {err:.2e}")
         assert err < 1e-5
+
+
+@pytest.mark.parametrize("m,k,n", [(9, 12, 4), (7, 11, 6), (4, 12, 9), (10, 16, 5), (12, 10, 10)])
+def test_splitk_single_step(torch, m, k, n):
+    """The split-K complex64 MFMA GEMM (kind 5) alone on one-step networks:
+    C = A B with 2^m x 2^k and 2^k x 2^n complex64 operands, every tile
+    configuration in both operand roles where it fits (from 2 to 256 chunks
+    of the sum), in every mode, against the exact product."""
+    import paper_2205_00393_amd as P
+    rng = np.random.default_rng(2000 + 100 * m + 10 * n + k)
+    M, K, N = 1 << m, 1 << k, 1 << n
+    a = (rng.standard_normal((M, K)) + 1j * rng.standard_normal((M, K))).astype(np.complex64)
+    b = (rng.standard_normal((K, N)) + 1j * rng.standard_normal((K, N))).astype(np.complex64)
+    mi, ki, ni = list(range(m)), list(range(m, m + k)), list(range(m + k, m + k + n))
+    net = P.Network.from_arrays([mi + ki, ki + ni], [a, b], mi + ni, m + k + n)
+    plan = P.Plan(net, [(0, 1)], [])
+    plan.bind(batch=1, budget_bytes=2 << 30)
+    exact = (a.astype(np.complex128) @ b.astype(np.complex128)).reshape(-1)
+    runs = 0
+    for mode in ("c64", "split_f16", "split_bf16"):
+        for swap in (0, 1):
+            for cfg in range(4):
+                try:
+                    plan.set_step_kernel(0, mode, 5, cfg, swap, 1)
+                except P.LtnError:
+                    continue
+                out = plan.execute([0], mode=mode)
+                torch.cuda.synchronize()
+                err = rel_l2(out.cpu().numpy(), exact)
+                banner(f"split-K ({m},{k},{n}) cfg {cfg} swap {swap} {mode}: rel err {err:.2e}")
+                assert err < 2e-5
+                runs += 1
+    assert runs > 0, "no split-K tile fits"
