@@ -331,13 +331,24 @@ __device__ __forceinline__ void generic_body(const GenericDesc& d, uint64_t blk,
     const float2* Q = d.Q + b * d.sQ + pdep(y, d.qy);
     float re = 0.f, im = 0.f;
     uint64_t zp = z0p, zq = z0q;
-    for (uint64_t z = lane; z < zc; z += TK) {
-      float2 p = P[zp], q = Q[zq];
-      if (d.conjQ) q.y = -q.y;
-      re += p.x * q.x - p.y * q.y;
-      im += p.x * q.y + p.y * q.x;
-      zp = madd(zp, zstep, d.pz);
-      zq = madd(zq, zstepq, d.qz);
+    // four iterations at a time, their eight loads issued before any product
+    // (a loop with one exit test per iteration keeps only two loads in flight)
+    for (uint64_t z = lane; z < zc; z += 4 * TK) {
+      float2 p[4], q[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool in = z + (uint64_t)j * TK < zc;
+        p[j] = in ? P[zp] : make_float2(0.f, 0.f);
+        q[j] = in ? Q[zq] : make_float2(0.f, 0.f);
+        zp = madd(zp, zstep, d.pz);
+        zq = madd(zq, zstepq, d.qz);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (d.conjQ) q[j].y = -q[j].y;
+        re += p[j].x * q[j].x - p[j].y * q[j].y;
+        im += p[j].x * q[j].y + p[j].y * q[j].x;
+      }
     }
     if (TK > 1) {
 #pragma unroll
