@@ -250,7 +250,7 @@ def time_plan(torch, P, pr, workload, modes, args, tag, fuse_rank=0, golden=None
         mf_flops, mf_bytes, mf_ms, mf_launch, split_flops = 0.0, 0.0, 0.0, 0, 0.0
         for k, st in enumerate(steps):
             kind, _, _, _ = plan.step_kernel(k, mode)
-            if kind in (1, 2):
+            if kind in (1, 2, 5):
                 f = 8.0 * (1 << (st["m"] + st["k"] + st["n"])) * batch
                 mf_flops += f
                 mf_bytes += 8.0 * ((1 << (st["m"] + st["k"])) + (1 << (st["n"] + st["k"])) +
@@ -407,18 +407,34 @@ def _csv_rows(d, suffix):
     return rows
 
 
-def _per_dispatch(d, counter, name_part=None):
+def _per_dispatch(d, counter, name_part=None, keep=None):
     """Counter value per dispatch (summed over the counter's dimensions),
-    for kernels whose name contains name_part (all when None)."""
+    for kernels whose name contains name_part (all when None); with keep,
+    only the last whole multiple of keep dispatches in dispatch order."""
     v = {}
     names = {}
     for r in _csv_rows(d, "counter_collection.csv"):
         if r["Counter_Name"] != counter or (name_part and name_part not in r["Kernel_Name"]):
             continue
-        key = (r["_file"], r["Dispatch_Id"])
+        key = (r["_file"], int(r["Dispatch_Id"]))
         v[key] = v.get(key, 0.0) + float(r["Counter_Value"])
         names[key] = r["Kernel_Name"]
+    if keep:
+        order = sorted(v)
+        order = order[len(order) - (len(order) // keep) * keep:]
+        v = {k: v[k] for k in order}
     return v, names
+
+
+def _durations(d, name_part, keep):
+    """Durations (ns) of the dispatches of kernels containing name_part, the
+    last whole multiple of keep in dispatch order (the launches of whole
+    batches: the autotuner's forward pass over its default choices runs
+    fewer of them before the first batch)."""
+    rows = sorted((int(x["Dispatch_Id"]), int(x["End_Timestamp"]) - int(x["Start_Timestamp"]))
+                  for x in _csv_rows(d, "kernel_trace.csv") if name_part in x["Kernel_Name"])
+    rows = rows[len(rows) - (len(rows) // keep) * keep:]
+    return [t for _, t in rows]
 
 
 def summarize_main(argv):
@@ -448,8 +464,7 @@ def summarize_main(argv):
     launches = r["mfma_launches_per_batch"]
     flops_l = r["mfma_flops_per_batch"] / launches
     bytes_l = r["mfma_alg_bytes_per_batch"] / launches
-    durs = [int(x["End_Timestamp"]) - int(x["Start_Timestamp"])
-            for x in _csv_rows(a.trace, "kernel_trace.csv") if a.kernel in x["Kernel_Name"]]
+    durs = _durations(a.trace, a.kernel, launches)
     avg_ms = sum(durs) / len(durs) / 1e6
     copy_bytes = a.copy_mib << 20
     cf, cfn = _per_dispatch(a.copy_fetch, "FETCH_SIZE")
@@ -458,8 +473,8 @@ def summarize_main(argv):
     kw = max(cw, key=cw.get)
     fetch_scale = copy_bytes / (cf[kf] * 1024.0)
     write_scale = copy_bytes / (cw[kw] * 1024.0)
-    f, _ = _per_dispatch(a.fetch, "FETCH_SIZE", a.kernel)
-    w, _ = _per_dispatch(a.write, "WRITE_SIZE", a.kernel)
+    f, _ = _per_dispatch(a.fetch, "FETCH_SIZE", a.kernel, launches)
+    w, _ = _per_dispatch(a.write, "WRITE_SIZE", a.kernel, launches)
     fetch_l = sum(f.values()) / len(f) * 1024.0 * fetch_scale
     write_l = sum(w.values()) / len(w) * 1024.0 * write_scale
     split = a.mode != "c64"
@@ -484,16 +499,15 @@ def summarize_main(argv):
           "in the same session).", "", "## Commands (repository root, `TMPDIR=/tmp`)", "", "```",
           open(a.commands).read().strip(), "```", ""]
     if a.mfma:
-        inst, _ = _per_dispatch(a.mfma, "SQ_INSTS_MFMA", a.kernel)
-        busy, _ = _per_dispatch(a.mfma, "SQ_VALU_MFMA_BUSY_CYCLES", a.kernel)
+        inst, _ = _per_dispatch(a.mfma, "SQ_INSTS_MFMA", a.kernel, launches)
+        busy, _ = _per_dispatch(a.mfma, "SQ_VALU_MFMA_BUSY_CYCLES", a.kernel, launches)
         n_inst = sum(inst.values())
         # flops per MFMA instruction: 32x32x2 FP32 = 4096, 32x32x16 f16/bf16 = 32768
         fpi = 32768 if split else 4096
         mc = {"dispatches": len(inst), "mfma_instructions": n_inst, "flops_per_instruction": fpi,
               "executed_flops": n_inst * fpi, "SQ_VALU_MFMA_BUSY_CYCLES": sum(busy.values())}
         # durations of the same dispatches from the counter run's own kernel trace
-        md_durs = [int(x["End_Timestamp"]) - int(x["Start_Timestamp"])
-                   for x in _csv_rows(a.mfma, "kernel_trace.csv") if a.kernel in x["Kernel_Name"]]
+        md_durs = _durations(a.mfma, a.kernel, launches)
         if md_durs and len(md_durs) == len(inst):
             tf = n_inst * fpi / (sum(md_durs) * 1e-9) / 1e12
             mc.update(duration_ms_total=sum(md_durs) / 1e6, executed_tflops_from_counters=tf,
