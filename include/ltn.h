@@ -483,9 +483,10 @@ ltn_status ltn_permute(const void* d_in, void* d_out, int32_t rank, const int32_
 
 /* Kernel chosen for a step in a mode after ltn_bind / ltn_autotune:
  * kind 0 = generic VALU kernel (tk threads per output), 1 = complex64 MFMA
- * GEMM, 2 = split-precision MFMA GEMM, 3 = narrow-step kernel (k + n <= 10,
- * n <= 6: A tile in LDS, B broadcast from LDS, outputs staged in address
- * order), 4 = split-sum kernel for steps with few outputs (m <= 3, n <= 3:
+ * GEMM, 2 = split-precision MFMA GEMM, 3 = narrow-step kernel (cfg 0:
+ * k + n <= 10, n <= 6, A tile in LDS, B broadcast from LDS, outputs staged
+ * in address order; cfg 1: k, n <= 4, m >= 8, one thread per row of A with
+ * all its loads in flight, B broadcast from LDS), 4 = split-sum kernel for steps with few outputs (m <= 3, n <= 3:
  * the sum over k is cut into chunks reduced by separate blocks, FP32
  * partials added in FP32 in a fixed order), 5 = split-K complex64 MFMA GEMM
  * (sums of 2^10 and more cut into chunks that separate blocks reduce on the

@@ -156,12 +156,121 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowDesc d) {
   }
 }
 
+__device__ __forceinline__ uint64_t madd_n(uint64_t a, uint64_t d, uint64_t mask) {
+  return ((a | ~mask) + d) & mask;
+}
+
+// Rows form: one thread per row of A. A block takes 256 consecutive rows
+// of one slice at a time; each thread issues the K / 2 16-byte loads of its
+// row (contiguous) at once, multiplies by B (N x K, broadcast from LDS) and
+// writes its N outputs. The output address of row r, column j is
+// pdep(chunk, cmask) | pdep(thread, cmask) | pdep(j, ~cmask): the first
+// part is advanced from chunk to chunk by a masked add, the second is fixed
+// per thread, the third is a table.
+template <int K, int N>
+__global__ __launch_bounds__(256) void k_narrow_rows(NarrowDesc d) {
+  __shared__ float2 Bs[N * K];
+  __shared__ uint64_t pj[N];
+  const int tid = threadIdx.x;
+  const uint64_t full = (d.m + d.n) >= 64 ? ~0ull : ((1ull << (d.m + d.n)) - 1);
+  if (tid < N) pj[tid] = pdep_n((uint64_t)tid, ~d.cmask & full);
+  const uint64_t pt = pdep_n((uint64_t)tid, d.cmask);
+  const int64_t R = int64_t(1) << d.m;
+  const int64_t chunks = (R >> 8) * d.nb;
+  const uint64_t step = pdep_n((uint64_t)gridDim.x << 8, d.cmask);
+  int64_t b_loaded = -1, r_prev = -1;
+  uint64_t base = 0;
+  float vmax = 0.f;
+  for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+    const int64_t b = (c << 8) >> d.m;
+    const int64_t r0 = (c << 8) - (b << d.m);
+    const float2* Ar = d.A + b * d.sA + (r0 + tid) * K;
+    float2 a[K];
+    if constexpr (K >= 2) {
+#pragma unroll
+      for (int kp = 0; kp < K / 2; ++kp) {
+        const float4 v = reinterpret_cast<const float4*>(Ar)[kp];
+        a[2 * kp] = make_float2(v.x, v.y);
+        a[2 * kp + 1] = make_float2(v.z, v.w);
+      }
+    } else {
+      a[0] = Ar[0];
+    }
+    if (b != b_loaded) {
+      if (b_loaded >= 0 && d.scale_c) {
+        float v = vmax;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+        if ((tid & 63) == 0) raise_max(d.scale_c + b_loaded, v);
+        vmax = 0.f;
+      }
+      __syncthreads();  // the previous slice's B is no longer read
+      const float2* Bb = d.B + b * d.sB;
+      for (int e = tid; e < N * K; e += 256) Bs[e] = Bb[e];
+      __syncthreads();
+      b_loaded = b;
+      base = pdep_n((uint64_t)r0, d.cmask);
+    } else {
+      base = r0 > r_prev ? madd_n(base, step, d.cmask) : pdep_n((uint64_t)r0, d.cmask);
+    }
+    r_prev = r0;
+    float2 acc[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) acc[j] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk)
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const float2 bv = Bs[j * K + kk];
+        acc[j].x += a[kk].x * bv.x - a[kk].y * bv.y;
+        acc[j].y += a[kk].x * bv.y + a[kk].y * bv.x;
+      }
+    float2* Cb = d.C + b * d.sC + (base | pt);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      Cb[pj[j]] = acc[j];
+      vmax = fmaxf(vmax, fmaxf(fabsf(acc[j].x), fabsf(acc[j].y)));
+    }
+  }
+  if (d.scale_c && b_loaded >= 0) {
+    float v = vmax;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    if ((tid & 63) == 0) raise_max(d.scale_c + b_loaded, v);
+  }
+}
+
+template <int K>
+void launch_rows_k(const NarrowDesc& d, dim3 grid, hipStream_t st) {
+  switch (d.n) {
+    case 0: hipLaunchKernelGGL((k_narrow_rows<K, 1>), grid, dim3(256), 0, st, d); break;
+    case 1: hipLaunchKernelGGL((k_narrow_rows<K, 2>), grid, dim3(256), 0, st, d); break;
+    case 2: hipLaunchKernelGGL((k_narrow_rows<K, 4>), grid, dim3(256), 0, st, d); break;
+    case 3: hipLaunchKernelGGL((k_narrow_rows<K, 8>), grid, dim3(256), 0, st, d); break;
+    default: hipLaunchKernelGGL((k_narrow_rows<K, 16>), grid, dim3(256), 0, st, d); break;
+  }
+}
+
 }  // namespace
 
 bool narrow_fits(int m, int k, int n) { return k + n <= 10 && n <= 6 && m >= 0 && m <= 40; }
 
+bool narrow_rows_fits(int m, int k, int n) { return k >= 0 && k <= 4 && n >= 0 && n <= 4 && m >= 8 && m <= 40; }
+
 void launch_narrow(const NarrowDesc& d0, hipStream_t st) {
   NarrowDesc d = d0;
+  if (d.cfg == 1) {
+    const int64_t chunks = ((int64_t(1) << d.m) >> 8) * d.nb;
+    const dim3 grid((unsigned)(chunks < 8192 ? chunks : 8192));
+    switch (d.k) {
+      case 0: launch_rows_k<1>(d, grid, st); break;
+      case 1: launch_rows_k<2>(d, grid, st); break;
+      case 2: launch_rows_k<4>(d, grid, st); break;
+      case 3: launch_rows_k<8>(d, grid, st); break;
+      default: launch_rows_k<16>(d, grid, st); break;
+    }
+    return;
+  }
   const int K = 1 << d.k, N = 1 << d.n;
   int mx = d.k > d.n ? d.k : d.n;
   d.q = d.m < 11 - mx ? d.m : 11 - mx;

@@ -126,11 +126,13 @@ struct NarrowDesc {
   int32_t m, k, n, nb;
   uint64_t cmask;
   uint32_t* scale_c;  // per-slice max slots of C, or null
+  int32_t cfg;        // 0: LDS-staged tiles; 1: one thread per row (k, n <= 4, m >= 8)
   // filled by launch_narrow
   int32_t q, a_elems;
   uint64_t tmask, rt, nt;
 };
 bool narrow_fits(int m, int k, int n);
+bool narrow_rows_fits(int m, int k, int n);
 void launch_narrow(const NarrowDesc& d, hipStream_t st);
 
 // Steps with few outputs and a long sum (m, n <= 3): C[merge(m, n)] =

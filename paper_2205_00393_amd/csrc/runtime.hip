@@ -279,6 +279,7 @@ void enqueue_step(ltn_plan* p, int s, int nb, bool gradarena, int mode) {
     d.k = sp.k;
     d.cmask = sw ? (~cm & full) : cm;
     d.nb = nb;
+    d.cfg = ch.cfg;
     if (mode == LTN_SPLIT_F16) d.scale_c = slot(p, sp.out);
     launch_narrow(d, r.st);
     return;
@@ -1310,9 +1311,14 @@ extern "C" ltn_status ltn_autotune(ltn_plan* p, int32_t mode, const char* cache_
     drop_graphs(p);
     // time on realistic values (power and clocks depend on the data): one
     // forward pass over slices 0.. fills every tensor of the arena, and in
-    // split-fp16 mode the per-slice maxima
-    set_ids(p, nullptr, 0, r.B, true);
-    enqueue_forward(p, r.B, false, mode == LTN_C64 ? LTN_C64 : mode);
+    // split-fp16 mode the per-slice maxima (not needed when every step's
+    // choice comes from the cache)
+    bool all_cached = true;
+    for (auto& sp : p->steps) all_cached = all_cached && cache.count(tune_key(mode, sp, r.B)) > 0;
+    if (!all_cached) {
+      set_ids(p, nullptr, 0, r.B, true);
+      enqueue_forward(p, r.B, false, mode == LTN_C64 ? LTN_C64 : mode);
+    }
     for (int s = 0; s < (int)p->steps.size(); ++s) {
       const StepPlan& sp = p->steps[s];
       std::string key = tune_key(mode, sp, r.B);
@@ -1334,7 +1340,7 @@ extern "C" ltn_status ltn_autotune(ltn_plan* p, int32_t mode, const char* cache_
                 cands.push_back(ch);
               }
         }
-        for (int sw = 0; sw < 2; ++sw)
+        for (int sw = 0; sw < 2; ++sw) {
           if (sw ? narrow_fits(sp.n, sp.k, sp.m) : narrow_fits(sp.m, sp.k, sp.n)) {
             Choice ch;
             ch.kind = 3;
@@ -1342,6 +1348,14 @@ extern "C" ltn_status ltn_autotune(ltn_plan* p, int32_t mode, const char* cache_
             ch.swap = sw;
             cands.push_back(ch);
           }
+          if (sw ? narrow_rows_fits(sp.n, sp.k, sp.m) : narrow_rows_fits(sp.m, sp.k, sp.n)) {
+            Choice ch;
+            ch.kind = 3;
+            ch.cfg = 1;
+            ch.swap = sw;
+            cands.push_back(ch);
+          }
+        }
         if (skinny_fits(sp.m, sp.k, sp.n)) {
           Choice ch;
           ch.kind = 4;
@@ -1456,9 +1470,11 @@ extern "C" ltn_status ltn_set_step_kernel(ltn_plan* p, int32_t step, int32_t mod
       c.cfg = cfg;
       c.swap = swap ? 1 : 0;
     } else if (kind == 3) {
-      require(narrow_fits(m, sp.k, n), "the narrow kernel does not fit the step");
+      require(cfg == 0 || cfg == 1, "narrow kernel configuration must be 0 or 1");
+      require(cfg == 0 ? narrow_fits(m, sp.k, n) : narrow_rows_fits(m, sp.k, n),
+              "the narrow kernel does not fit the step");
       c.kind = 3;
-      c.cfg = 0;
+      c.cfg = cfg;
       c.swap = swap ? 1 : 0;
     } else if (kind == 4) {
       require(skinny_fits(sp.m, sp.k, sp.n), "the split-sum kernel needs m <= 3 and n <= 3");

@@ -1,5 +1,5 @@
 """Every kernel a step can run, forced step by step through
-ltn_set_step_kernel: narrow-step kernel in both operand roles, generic
+ltn_set_step_kernel: narrow-step kernel (both forms) in both operand roles, generic
 kernel with 1, 8 and 64 threads per output, complex64 MFMA tiles, and the
 split tiles (register- and DMA-staged) in the split modes. Each forced plan must reproduce the
 brute-force state-vector amplitudes (complex64 <= 1e-4, split <= 5e-4).
@@ -16,6 +16,8 @@ pytestmark = pytest.mark.gpu
 VARIANTS = {
     "narrow_rows_a": [(3, 0, 0, 1)],
     "narrow_rows_b": [(3, 0, 1, 1)],
+    # the narrow kernel's one-thread-per-row form (k, n <= 4, m >= 8)
+    "narrow_thread_rows_a": [(3, 1, 0, 1)],
     "generic_tk1": [(0, -1, 0, 1)],
     "generic_tk8": [(0, -1, 0, 8)],
     "generic_tk64": [(0, -1, 0, 64)],
@@ -212,3 +214,36 @@ def test_splitk_single_step(torch, m, k, n):
                 assert err < 2e-5
                 runs += 1
     assert runs > 0, "no split-K tile fits"
+
+
+@pytest.mark.parametrize("m,k,n", [(9, 0, 1), (10, 2, 3), (3, 2, 10), (12, 4, 4), (4, 1, 11), (22, 2, 2)])
+def test_narrow_rows_single_step(torch, m, k, n):
+    """The narrow kernel's one-thread-per-row form alone on one-step
+    networks (the plan puts the large operand in the rows role, so (3,2,10)
+    and (4,1,11) run as (10,2,3) and (11,1,4)), in every mode, against the
+    exact product; at m = 22 the blocks take several 256-row chunks of the
+    slice, so the output address is advanced by the masked add."""
+    import paper_2205_00393_amd as P
+    rng = np.random.default_rng(3000 + 100 * m + 10 * n + k)
+    M, K, N = 1 << m, 1 << k, 1 << n
+    a = (rng.standard_normal((M, K)) + 1j * rng.standard_normal((M, K))).astype(np.complex64)
+    b = (rng.standard_normal((K, N)) + 1j * rng.standard_normal((K, N))).astype(np.complex64)
+    mi, ki, ni = list(range(m)), list(range(m, m + k)), list(range(m + k, m + k + n))
+    net = P.Network.from_arrays([mi + ki, ki + ni], [a, b], mi + ni, m + k + n)
+    plan = P.Plan(net, [(0, 1)], [])
+    plan.bind(batch=1, budget_bytes=2 << 30)
+    exact = (a.astype(np.complex128) @ b.astype(np.complex128)).reshape(-1)
+    runs = 0
+    for mode in ("c64", "split_f16", "split_bf16"):
+        for swap in (0, 1):
+            try:
+                plan.set_step_kernel(0, mode, 3, 1, swap, 1)
+            except P.LtnError:
+                continue
+            out = plan.execute([0], mode=mode)
+            torch.cuda.synchronize()
+            err = rel_l2(out.cpu().numpy(), exact)
+            banner(f"narrow rows ({m},{k},{n}) swap {swap} {mode}: rel err {err:.2e}")
+            assert err < 1e-5
+            runs += 1
+    assert runs == 3, "the rows form must fit one operand role"
