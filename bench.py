@@ -8,9 +8,11 @@ taken in order from the seeded subset of 1024 slice ids; successive steps
 walk the subset. complex64 is the headline; split fp16 and split bf16 are
 timed beside it; each mode states its error on the stored oracle slices.
 
-Extra keys: the 30-qubit workload (every slice per step, greedy and
-reconfigured paths, fused sub-paths), the 20-qubit gradient workload, and
-CPU oracle timings of each.
+Extra keys: path_variant (the same circuit on the greedy trials improved
+by subtree reconfiguration, errors on its own two stored oracle slices),
+the 30-qubit workload (every slice per step, greedy and reconfigured
+paths, fused sub-paths), the 20-qubit gradient workload, and CPU oracle
+timings of each.
 
 Prints one JSON line. Inputs are synthetic (seeded circuits); the host
 planner runs before the timed regions.
@@ -247,20 +249,34 @@ def time_plan(torch, P, pr, workload, modes, args, tag, fuse_rank=0, golden=None
         for _ in range(reps):
             ms += plan.profile_steps(first, mode)
         ms /= reps
-        mf_flops, mf_bytes, mf_ms, mf_launch, split_flops = 0.0, 0.0, 0.0, 0, 0.0
+        # matrix-core steps: kinds 1 and 5 run k_cgemm_c64 (complex64, the
+        # split-K form included), kind 2 runs k_cgemm_split
+        fam = {"k_cgemm_c64": (1, 5), "k_cgemm_split": (2,), "k_narrow": (3,)}
+        kern = {name: {"launches": 0, "flops_per_batch": 0.0, "alg_bytes_per_batch": 0.0,
+                       "ms_per_batch": 0.0} for name in fam}
+        mf_flops, mf_ms, mf_launch, split_flops = 0.0, 0.0, 0, 0.0
         for k, st in enumerate(steps):
             kind, _, _, _ = plan.step_kernel(k, mode)
-            if kind in (1, 2, 5):
-                f = 8.0 * (1 << (st["m"] + st["k"] + st["n"])) * batch
-                mf_flops += f
-                mf_bytes += 8.0 * ((1 << (st["m"] + st["k"])) + (1 << (st["n"] + st["k"])) +
-                                   (1 << (st["m"] + st["n"]))) * batch
-                mf_ms += ms[k]
-                mf_launch += 1
-                if kind == 2:
-                    split_flops += f
-        res["mfma_flops_per_batch"] = mf_flops
-        res["mfma_alg_bytes_per_batch"] = mf_bytes
+            for name, kinds in fam.items():
+                if kind in kinds:
+                    f = 8.0 * (1 << (st["m"] + st["k"] + st["n"])) * batch
+                    e = kern[name]
+                    e["launches"] += 1
+                    e["flops_per_batch"] += f
+                    e["alg_bytes_per_batch"] += 8.0 * ((1 << (st["m"] + st["k"])) + (1 << (st["n"] + st["k"])) +
+                                                       (1 << (st["m"] + st["n"]))) * batch
+                    e["ms_per_batch"] += ms[k]
+                    if name == "k_narrow":
+                        continue
+                    mf_flops += f
+                    mf_ms += ms[k]
+                    mf_launch += 1
+                    if kind == 2:
+                        split_flops += f
+        for e in kern.values():
+            e["alg_tflops"] = e["flops_per_batch"] / (e["ms_per_batch"] * 1e-3) / 1e12 if e["ms_per_batch"] > 0 else 0.0
+            e["alg_gbs"] = e["alg_bytes_per_batch"] / (e["ms_per_batch"] * 1e-3) / 1e9 if e["ms_per_batch"] > 0 else 0.0
+        res["kernels"] = kern
         res["mfma_ms_per_batch"] = mf_ms
         res["step_ms_per_batch"] = float(ms.sum())
         res["mfma_launches_per_batch"] = mf_launch
@@ -282,32 +298,35 @@ def time_plan(torch, P, pr, workload, modes, args, tag, fuse_rank=0, golden=None
 def mode_table(results):
     out = {}
     for m, r in results.items():
-        out[m] = {k: (sig6(v) if not isinstance(v, list) else v) for k, v in r.items()}
+        out[m] = {k: (sig6(v) if not isinstance(v, (list, dict)) else v) for k, v in r.items()}
         out[m]["speedup_vs_c64"] = round(r["tflops"] / results["c64"]["tflops"], 4) if "c64" in results else None
         out[m]["meets_tolerance"] = (r.get("rel_l2_error") is not None and r["rel_l2_error"] <= TOL[m])
     return out
 
 
 def roofline_of(workload, mode, r):
+    """The mode's dominant kernel: the complex64 GEMM (algorithmic flops =
+    executed) or the split GEMM (three fp16/bf16 matrix products per real
+    product: executed flops are 3x the algorithmic count), over its own
+    launches only."""
+    kernel = "k_cgemm_c64" if mode == "c64" else "k_cgemm_split"
+    e = r["kernels"][kernel]
     if mode == "c64":
-        peak, achieved = PEAK_FP32_MFMA_TFLOPS, r["mfma_tflops"]
+        peak, achieved = PEAK_FP32_MFMA_TFLOPS, e["alg_tflops"]
     else:
-        # split: three fp16/bf16 matrix products per real product; executed
-        # matrix flops are 3x the algorithmic count
-        peak, achieved = PEAK_F16_MFMA_TFLOPS, 3.0 * r["mfma_tflops"]
+        peak, achieved = PEAK_F16_MFMA_TFLOPS, 3.0 * e["alg_tflops"]
     return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": counter_traffic(workload, mode),
-            "kernel": "k_cgemm_c64" if mode == "c64" else "k_cgemm_split",
-            "launches_per_batch": r["mfma_launches_per_batch"],
-            "share_of_step_time": round(r["mfma_ms_per_batch"] / r["step_ms_per_batch"], 4)}
+            "kernel": kernel, "launches_per_batch": e["launches"],
+            "share_of_step_time": round(e["ms_per_batch"] / r["step_ms_per_batch"], 4)}
 
 
-def rqc53_golden():
-    path = os.path.join(GOLDEN, "rqc53_slices.npz")
+def rqc53_golden(stem="rqc53_slices"):
+    path = os.path.join(GOLDEN, stem + ".npz")
     if not os.path.exists(path):
         return None, None
     z = np.load(path)
-    meta = json.load(open(os.path.join(GOLDEN, "rqc53_slices.json")))
+    meta = json.load(open(os.path.join(GOLDEN, stem + ".json")))
     return {"positions": z["positions"], "amplitudes": list(z["amplitudes"]),
             "ids": [int(r["id"]) for r in meta["slices"]],
             "norm2": [r["norm2"] for r in meta["slices"]]}, meta
@@ -456,14 +475,17 @@ def summarize_main(argv):
         ap.add_argument(a, required=True)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--mfma", default=None)
+    ap.add_argument("--bound", default="mfma", choices=["mfma", "hbm"],
+                    help="hbm: report achieved algorithmic GB/s against the 8 TB/s HBM peak")
     a = ap.parse_args(argv)
     line = json.loads(open(a.bench).read().strip().splitlines()[-1])
     r = line["modes"][a.mode] if a.workload in line["config"]["workload"] else \
         line[a.workload]["modes"][a.mode]
     batch = line["config"]["batch"] if a.workload in line["config"]["workload"] else line[a.workload]["batch"]
-    launches = r["mfma_launches_per_batch"]
-    flops_l = r["mfma_flops_per_batch"] / launches
-    bytes_l = r["mfma_alg_bytes_per_batch"] / launches
+    e = r["kernels"][a.kernel]
+    launches = e["launches"]
+    flops_l = e["flops_per_batch"] / launches
+    bytes_l = e["alg_bytes_per_batch"] / launches
     durs = _durations(a.trace, a.kernel, launches)
     avg_ms = sum(durs) / len(durs) / 1e6
     copy_bytes = a.copy_mib << 20
@@ -477,16 +499,18 @@ def summarize_main(argv):
     w, _ = _per_dispatch(a.write, "WRITE_SIZE", a.kernel, launches)
     fetch_l = sum(f.values()) / len(f) * 1024.0 * fetch_scale
     write_l = sum(w.values()) / len(w) * 1024.0 * write_scale
-    split = a.mode != "c64"
+    split = a.mode != "c64" and a.kernel == "k_cgemm_split"
     peak = PEAK_F16_MFMA_TFLOPS if split else PEAK_FP32_MFMA_TFLOPS
     alg_tf = flops_l / (avg_ms * 1e-3) / 1e12
     exe_tf = alg_tf * (3.0 if split else 1.0)
+    alg_gbs = bytes_l / (avg_ms * 1e-3) / 1e9
     src = open(os.path.join(ROOT, "paper_2205_00393_amd", "csrc", "k_mfma.hip"), "rb").read()
     rec = {"kernel": a.kernel, "workload": a.workload, "mode": a.mode, "batch": batch,
            "launches_per_batch": launches, "avg_launch_ms": avg_ms, "calls": len(durs),
            "alg_flops_per_launch": flops_l, "alg_bytes_per_launch": bytes_l,
            "achieved_alg_tflops": alg_tf, "executed_matrix_tflops": exe_tf, "peak_tflops": peak,
-           "frac_of_peak": exe_tf / peak,
+           "frac_of_peak": exe_tf / peak if a.bound == "mfma" else alg_gbs / PEAK_HBM_GBS,
+           "bound": a.bound, "achieved_alg_gbs": alg_gbs, "peak_gbs": PEAK_HBM_GBS,
            "hbm_fetch_bytes_per_launch": fetch_l, "hbm_write_bytes_per_launch": write_l,
            "traffic_bytes_per_launch": fetch_l + write_l,
            "traffic_over_algorithmic": (fetch_l + write_l) / bytes_l,
@@ -513,11 +537,17 @@ def summarize_main(argv):
             mc.update(duration_ms_total=sum(md_durs) / 1e6, executed_tflops_from_counters=tf,
                       frac_of_peak_from_counters=tf / peak)
         rec["mfma_counters"] = mc
-    md += ["## Figures", "",
-           f"* {a.kernel}: {launches} launches per batch, average {avg_ms:.3f} ms per launch "
-           f"({len(durs)} launches traced); algorithmic flops per launch (8 per complex MAC) "
-           f"{flops_l:.4e} -> {alg_tf:.1f} TFLOP/s algorithmic, {exe_tf:.1f} TFLOP/s executed on the "
-           f"matrix cores = {100 * exe_tf / peak:.1f} % of the {peak} TFLOP/s dense peak.",
+    if a.bound == "mfma":
+        first = (f"* {a.kernel}: {launches} launches per batch, average {avg_ms:.3f} ms per launch "
+                 f"({len(durs)} launches traced); algorithmic flops per launch (8 per complex MAC) "
+                 f"{flops_l:.4e} -> {alg_tf:.1f} TFLOP/s algorithmic, {exe_tf:.1f} TFLOP/s executed on the "
+                 f"matrix cores = {100 * exe_tf / peak:.1f} % of the {peak} TFLOP/s dense peak.")
+    else:
+        first = (f"* {a.kernel}: {launches} launches per batch, average {avg_ms:.4f} ms per launch "
+                 f"({len(durs)} launches traced); algorithmic bytes per launch (A + B + C once) "
+                 f"{bytes_l:.4e} -> {alg_gbs:.0f} GB/s = {100 * alg_gbs / PEAK_HBM_GBS:.1f} % of the "
+                 f"{PEAK_HBM_GBS:.0f} GB/s HBM peak (aggregate over the launches of a batch).")
+    md += ["## Figures", "", first,
            f"* HBM traffic per launch: fetch {fetch_l:.4e} B + write {write_l:.4e} B = "
            f"{fetch_l + write_l:.4e} B against {bytes_l:.4e} B algorithmic (A + B + C once) = "
            f"{(fetch_l + write_l) / bytes_l:.2f} x.",
@@ -562,7 +592,11 @@ def main():
                          "gradient); '' for none")
     ap.add_argument("--rqc30-modes", default="c64,split_f16,split_bf16")
     ap.add_argument("--path-variant", default="c64,split_bf16",
-                    help="rqc30 modes to time on the reconfigured path as well ('' to skip)")
+                    help="modes to time on the reconfigured path as well, for the headline "
+                         "workload and the rqc30 leg ('' to skip)")
+    ap.add_argument("--reconf-k", type=int, default=0,
+                    help="headline plan on the greedy trials improved by subtree reconfiguration with "
+                         "this window (0: the randomised greedy path, the workloads' definition)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--no-golden", action="store_true",
                     help="skip the error checks on stored oracle slices (profiled runs: they launch "
@@ -599,28 +633,57 @@ def main():
     if args.workload == "rqc53":
         w = make_workload("rqc53")
         t0 = time.perf_counter()
-        pr = P.prepare(w)
+        pr = P.prepare(w, reconf_k=args.reconf_k)
         t_plan = time.perf_counter() - t0
         log(f"[rqc53] host planner (randomised greedy search + Algorithm 1) {t_plan:.2f}s")
-        golden, meta = rqc53_golden() if not args.no_golden else (None, None)
+        golden, meta = rqc53_golden("rqc53_reconf_slices" if args.reconf_k else "rqc53_slices") \
+            if not args.no_golden else (None, None)
         if meta is not None and meta["sliced"] != pr.sliced:
             log("[rqc53] the stored oracle slices belong to another slicing set; no error reported")
             golden = None
         results, f = time_plan(torch, P, pr, "rqc53", modes, args, "rqc53", golden=golden)
         walked = f["per_step"] * args.steps
-        wl = (f"{WORKLOAD_TEXT['rqc53']}, randomised greedy path, |S|={f['n_sliced']}; one step = one "
+        pathtxt = f"randomised greedy path + subtree reconfiguration (k={args.reconf_k})" if args.reconf_k \
+            else "randomised greedy path"
+        wl = (f"{WORKLOAD_TEXT['rqc53']}, {pathtxt}, |S|={f['n_sliced']}; one step = one "
               f"batch of {f['per_step']} slices walking the seeded subset of 1024 slice ids "
               f"(seed 3); {walked} slices timed")
+        variant = None
+        if args.path_variant and not args.reconf_k:
+            # the same circuit on the greedy trials improved by subtree
+            # reconfiguration (window 8): fewer sliced indices, less work per slice
+            t0 = time.perf_counter()
+            prv = P.prepare(w, reconf_k=8)
+            t_planv = time.perf_counter() - t0
+            gv, mv = rqc53_golden("rqc53_reconf_slices") if not args.no_golden else (None, None)
+            if mv is not None and mv["sliced"] != prv.sliced:
+                gv = None
+            vres, vf = time_plan(torch, P, prv, "rqc53", args.path_variant.split(","), args, "rqc53 reconf",
+                                 golden=gv)
+            variant = {"path": "randomised greedy + subtree reconfiguration (k=8)",
+                       "plan_seconds": round(t_planv, 3), "sliced_indices": vf["n_sliced"],
+                       "log2_C_BS": round(vf["costs"].log2_sliced, 4), "macs_per_slice": vf["macs_slice"],
+                       "batch": vf["batch"],
+                       "projected_seconds_all_slices": {m: r["sec_per_slice"] * 2.0 ** vf["n_sliced"]
+                                                        for m, r in vres.items()},
+                       "modes": mode_table(vres)}
+            for m, r in vres.items():
+                if m in results:
+                    variant["modes"][m]["time_to_solution_speedup_vs_greedy_path"] = float(
+                        (results[m]["sec_per_slice"] * 2.0 ** f["n_sliced"]) /
+                        (r["sec_per_slice"] * 2.0 ** vf["n_sliced"]))
     else:
         w = make_workload("rqc30")
         t0 = time.perf_counter()
-        pr = P.prepare(w)
+        pr = P.prepare(w, reconf_k=args.reconf_k)
         t_plan = time.perf_counter() - t0
         ref_path = os.path.join(GOLDEN, "rqc30_amplitudes.npy")
         golden = {"amplitudes": np.load(ref_path)} if os.path.exists(ref_path) and not args.no_golden else None
         results, f = time_plan(torch, P, pr, "rqc30", modes, args, "rqc30", golden=golden)
-        wl = WORKLOAD_TEXT["rqc30"] + ", all slices per step, randomised greedy path"
+        wl = WORKLOAD_TEXT["rqc30"] + ", all slices per step, randomised greedy path" + \
+            (f" + subtree reconfiguration (k={args.reconf_k})" if args.reconf_k else "")
         extras = [e for e in extras if e != "rqc30"]
+        variant = None
     r0 = results[main_mode]
     n_sliced = f["n_sliced"]
     line = {
@@ -636,7 +699,9 @@ def main():
         "vs_baseline": None,
         "dtype": {"c64": "c64", "split_f16": "f16x2", "split_bf16": "bf16x2"}[main_mode],
         "data": "synthetic",
-        "config": {"workload": wl, "mode": main_mode, "path": "randomised greedy",
+        "config": {"workload": wl, "mode": main_mode,
+                   "path": "randomised greedy" + (f" + subtree reconfiguration (k={args.reconf_k})"
+                                                  if args.reconf_k else ""),
                    "slices_per_step": f["per_step"], "batch": f["batch"], "sliced_indices": n_sliced,
                    "log2_C_BS": round(f["costs"].log2_sliced, 4), "overhead": round(f["costs"].overhead, 5),
                    "macs_per_slice": f["macs_slice"], "flops_per_step": f["flops_step"],
@@ -650,6 +715,8 @@ def main():
         "roofline": roofline_of(args.workload, main_mode, r0),
         "cpu_baseline": None,
     }
+    if args.workload == "rqc53" and variant is not None:
+        line["path_variant"] = variant
     if "rqc30" in extras:
         line["rqc30"] = rqc30_extra(torch, P, args)
     if "grad" in extras:

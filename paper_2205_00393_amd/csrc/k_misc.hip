@@ -162,23 +162,25 @@ __global__ void __launch_bounds__(64) k_reduce_lanes(const float2* __restrict__ 
       for (int c = 0; c < nb; c += 64) {
         const int b = c + lane;
         const bool mine = b < nb;
-        double xr = 0, xi = 0;
-        unsigned long long key = ~0ull;
+        float2 v = make_float2(0.f, 0.f);
+        uint64_t key = ~0ull;
         if (mine) {
-          const float2 v = root[(int64_t)b * n + e];
-          xr = v.x;
-          xi = v.y;
+          v = root[(int64_t)b * n + e];
           key = placement(0, 0, so, n_sl, ids[b]);
         }
+        const uint32_t klo = (uint32_t)key, khi = (uint32_t)(key >> 32);
         double sr = 0, si = 0;
         bool lowest = true;
         const int lim = nb - c < 64 ? nb - c : 64;
+        // lane i's key and value, read into scalar registers (i is uniform)
         for (int i = 0; i < lim; ++i) {
-          const unsigned long long ki = __shfl(key, i);
-          const double vr = __shfl(xr, i), vi = __shfl(xi, i);
-          if (ki == key) {
-            sr += vr;
-            si += vi;
+          const uint32_t ilo = (uint32_t)__builtin_amdgcn_readlane((int)klo, i);
+          const uint32_t ihi = (uint32_t)__builtin_amdgcn_readlane((int)khi, i);
+          const float vr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), i));
+          const float vi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), i));
+          if (ilo == klo && ihi == khi) {
+            sr += (double)vr;
+            si += (double)vi;
             if (i < lane) lowest = false;
           }
         }
