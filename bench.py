@@ -40,6 +40,10 @@ WORKLOAD_TEXT = {
 }
 
 
+# source file of each profiled kernel family (its hash marks the counters stale)
+KERNEL_SOURCE = {"k_cgemm_c64": "k_mfma.hip", "k_cgemm_split": "k_mfma.hip", "k_narrow": "k_narrow.hip"}
+
+
 def counter_traffic(workload, mode):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter summary for this workload and mode, or None when there
@@ -504,7 +508,8 @@ def summarize_main(argv):
     alg_tf = flops_l / (avg_ms * 1e-3) / 1e12
     exe_tf = alg_tf * (3.0 if split else 1.0)
     alg_gbs = bytes_l / (avg_ms * 1e-3) / 1e9
-    src = open(os.path.join(ROOT, "paper_2205_00393_amd", "csrc", "k_mfma.hip"), "rb").read()
+    src_name = KERNEL_SOURCE.get(a.kernel, "k_mfma.hip")
+    src = open(os.path.join(ROOT, "paper_2205_00393_amd", "csrc", src_name), "rb").read()
     rec = {"kernel": a.kernel, "workload": a.workload, "mode": a.mode, "batch": batch,
            "launches_per_batch": launches, "avg_launch_ms": avg_ms, "calls": len(durs),
            "alg_flops_per_launch": flops_l, "alg_bytes_per_launch": bytes_l,
@@ -515,7 +520,7 @@ def summarize_main(argv):
            "traffic_bytes_per_launch": fetch_l + write_l,
            "traffic_over_algorithmic": (fetch_l + write_l) / bytes_l,
            "fetch_scale": fetch_scale, "write_scale": write_scale,
-           "copy_kernel": cfn[kf], "source_sha256": hashlib.sha256(src).hexdigest(),
+           "copy_kernel": cfn[kf], "source": src_name, "source_sha256": hashlib.sha256(src).hexdigest(),
            "bench_tflops": line["value"] if a.workload in line["config"]["workload"] else None}
     md = [f"# {a.kernel} on the {a.workload} workload ({a.mode})", "",
           f"Workload: {line['config']['workload'] if a.workload in line['config']['workload'] else line[a.workload]['workload']}.",
@@ -553,7 +558,7 @@ def summarize_main(argv):
            f"{(fetch_l + write_l) / bytes_l:.2f} x.",
            f"* Counter scale from a {a.copy_mib} MiB device copy (`{cfn[kf][:60]}`): FETCH_SIZE x "
            f"{fetch_scale:.4f}, WRITE_SIZE x {write_scale:.4f}.",
-           f"* k_mfma.hip sha256 at measurement: `{rec['source_sha256']}`"]
+           f"* {src_name} sha256 at measurement: `{rec['source_sha256']}`"]
     if "mfma_counters" in rec and "executed_tflops_from_counters" in rec["mfma_counters"]:
         mc = rec["mfma_counters"]
         md.append(f"* MFMA instruction counters: {mc['mfma_instructions']:.4e} instructions x "

@@ -125,10 +125,13 @@ __global__ void k_reduce(const float2* __restrict__ root, int rank, uint64_t out
 // slice adds into the same target: a fixed butterfly of FP64 shuffles sums
 // each chunk, lane 0 adds the chunks in order and writes once. With sliced
 // open indices a slice's target also carries its sliced open bits (its
-// key): each lane adds, in ascending lane order, the values of the lanes
-// with its key, and the lowest lane of each key writes; blocks are one
-// wave and chunks are separated by a barrier, so a chunk sees the writes
-// of the chunks before it.
+// key): the wave sorts (key, lane) pairs with a bitonic network of
+// shuffles, fetches the values in that order, and a segmented FP64 shuffle
+// scan over the sorted lanes leaves each key's sum on the last lane of its
+// run, which writes it. The addition tree depends only on the keys' lane
+// positions, so reruns are bit-identical. Up to four chunks are loaded
+// before the first is summed; chunks are separated by a barrier, so a chunk
+// sees the writes of the chunks before it.
 __global__ void __launch_bounds__(64) k_reduce_lanes(const float2* __restrict__ root, int rank,
                                                      uint64_t out_mask, SliceOut so, int n_sl,
                                                      const uint64_t* __restrict__ ids, int nb,
@@ -159,37 +162,64 @@ __global__ void __launch_bounds__(64) k_reduce_lanes(const float2* __restrict__ 
         out[2 * base + 1] += im;
       }
     } else {
-      for (int c = 0; c < nb; c += 64) {
-        const int b = c + lane;
-        const bool mine = b < nb;
-        float2 v = make_float2(0.f, 0.f);
-        uint64_t key = ~0ull;
-        if (mine) {
-          v = root[(int64_t)b * n + e];
-          key = placement(0, 0, so, n_sl, ids[b]);
-        }
-        const uint32_t klo = (uint32_t)key, khi = (uint32_t)(key >> 32);
-        double sr = 0, si = 0;
-        bool lowest = true;
-        const int lim = nb - c < 64 ? nb - c : 64;
-        // lane i's key and value, read into scalar registers (i is uniform)
-        for (int i = 0; i < lim; ++i) {
-          const uint32_t ilo = (uint32_t)__builtin_amdgcn_readlane((int)klo, i);
-          const uint32_t ihi = (uint32_t)__builtin_amdgcn_readlane((int)khi, i);
-          const float vr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), i));
-          const float vi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), i));
-          if (ilo == klo && ihi == khi) {
-            sr += (double)vr;
-            si += (double)vi;
-            if (i < lane) lowest = false;
+      for (int c0 = 0; c0 < nb; c0 += 256) {
+        float2 v[4];
+        uint64_t id[4], key[4];
+        uint32_t ck[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {  // all loads issued before any use
+          const int b = c0 + 64 * j + lane;
+          v[j] = make_float2(0.f, 0.f);
+          id[j] = 0;
+          if (b < nb) {
+            v[j] = root[(int64_t)b * n + e];
+            id[j] = ids[b];
           }
         }
-        if (mine && lowest) {
-          const uint64_t p = base | key;
-          out[2 * p] += sr;
-          out[2 * p + 1] += si;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          key[j] = 0;
+          ck[j] = 0;
+          if (c0 + 64 * j < nb)
+            for (int i = 0; i < n_sl; ++i) {
+              const uint64_t bit = (id[j] >> so.sl[i]) & 1;
+              key[j] |= bit << so.ob[i];
+              ck[j] |= (uint32_t)bit << i;
+            }
         }
-        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = c0 + 64 * j;
+          if (c >= nb) break;
+          // sort key: compact key above the lane (lanes past the batch last)
+          const uint64_t grp = c + lane < nb ? (uint64_t)ck[j] : (1ull << 32);
+          uint64_t sk = (grp << 6) | (uint64_t)lane;
+          for (int k = 2; k <= 64; k <<= 1)
+            for (int h = k >> 1; h > 0; h >>= 1) {
+              const uint64_t o = __shfl_xor(sk, h, 64);
+              const bool up = (lane & k) == 0, low = (lane & h) == 0;
+              sk = (low == up) ? (o < sk ? o : sk) : (o > sk ? o : sk);
+            }
+          const int src = (int)(sk & 63);
+          const uint64_t g = sk >> 6;
+          double sr = (double)__shfl(v[j].x, src, 64);
+          double si = (double)__shfl(v[j].y, src, 64);
+          const uint64_t p = base | __shfl(key[j], src, 64);
+          for (int d = 1; d < 64; d <<= 1) {
+            const double pr = __shfl_up(sr, d, 64), pi = __shfl_up(si, d, 64);
+            const uint64_t pg = __shfl_up(g, d, 64);
+            if (lane >= d && pg == g) {
+              sr += pr;
+              si += pi;
+            }
+          }
+          const uint64_t ng = __shfl_down(g, 1, 64);
+          if (g < (1ull << 32) && (lane == 63 || ng != g)) {
+            out[2 * p] += sr;
+            out[2 * p + 1] += si;
+          }
+          __syncthreads();
+        }
       }
     }
   }
