@@ -274,6 +274,9 @@ __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
   for (int g = 0; g < 4; ++g) pg[g] = pdep64((uint64_t)(8 * g), maskA);
 #pragma unroll
   for (int x = 0; x < C::TM; ++x) pt[x] = pdep64((uint64_t)(32 * x), maskA);
+  // the output's two lowest bits are row bits 0 and 1: a lane's four
+  // accumulators q = 0..3 are four consecutive outputs (16-byte stores)
+  const bool rows4 = (maskA & 3) == 3;
   float vmax = 0.f;
 #pragma unroll
   for (int y = 0; y < C::TN; ++y) {
@@ -282,7 +285,40 @@ __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
 #pragma unroll
     for (int x = 0; x < C::TM; ++x)
 #pragma unroll
-      for (int g = 0; g < 4; ++g)
+      for (int g = 0; g < 4; ++g) {
+        if (rows4) {
+          const uint64_t a0 = pbase | pt[x] | pg[g] | pn;
+          float v[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            v[q] = acc[x][y][4 * g + q];
+            vmax = fmaxf(vmax, fabsf(v[q]));
+          }
+          if (!SPLITK && d.split_out) {
+            // the even lane writes the four hi words, the odd lane the lo words
+            uint32_t wd[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const float o = __shfl_xor(v[q], 1, 64);
+              const float re = im_col ? o : v[q], im = im_col ? v[q] : o;
+              uint32_t lo, hi;
+              if (d.split_out == 1)
+                hi = split_pair<true>(re, im, 1.f, lo);
+              else
+                hi = split_pair<false>(re, im, so, lo);
+              wd[q] = im_col ? lo : hi;
+            }
+            *reinterpret_cast<uint4*>(Cw + (a0 >> 2) * 8 + (im_col ? 4 : 0)) =
+                make_uint4(wd[0], wd[1], wd[2], wd[3]);
+          } else {
+            // even lane (re parts): outputs 0, 1; odd lane (im parts): outputs 2, 3
+            const float s0 = __shfl_xor(im_col ? v[0] : v[2], 1, 64);
+            const float s1 = __shfl_xor(im_col ? v[1] : v[3], 1, 64);
+            *reinterpret_cast<float4*>(Cf + 2 * a0 + (im_col ? 4 : 0)) =
+                im_col ? make_float4(s0, v[2], s1, v[3]) : make_float4(v[0], s0, v[1], s1);
+          }
+          continue;
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           uint64_t addr = pbase | pt[x] | pg[g] | pq[q] | pn;
@@ -303,6 +339,7 @@ __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
             Cf[2 * addr + (im_col ? 1 : 0)] = v;
           }
         }
+      }
   }
   if (!SPLITK && d.scale_c) record_max(d.scale_c + b, vmax);
 }
@@ -381,13 +418,14 @@ __global__ __launch_bounds__(256) void k_split_convert(const float2* X, float2* 
   }
 }
 
-// Split GEMM tile: 4 waves in 2 x 2, wave tile (BM/2) rows x (BNC/2)
+// Split GEMM tile: NWM x NWN waves, wave tile (BM/NWM) rows x (BNC/NWN)
 // complex columns. MFMA columns are complex outputs: each lane reads its B
 // value once and forms both real-form rows of it, (re, -im) for the real
-// accumulator and (im, re) for the imaginary one.
-template <int BM, int BNC, int BKC, int NWN>
+// accumulator and (im, re) for the imaginary one; the forms of one B
+// fragment feed the wave's TM row tiles.
+template <int BM, int BNC, int BKC, int NWN, int NWM = 2>
 struct SplitCfg {
-  static constexpr int WM = BM / 2, TM = WM / 32;
+  static constexpr int WM = BM / NWM, TM = WM / 32;
   static constexpr int WNC = BNC / NWN, TN = WNC / 32;
   static_assert(TM >= 1 && TN >= 1 && BKC % 8 == 0, "tile too small for the split GEMM");
 };
@@ -407,14 +445,16 @@ struct SplitCfg {
 //    sw(r) = (r / (16 / U)) mod U: 16 consecutive rows at one group then fall
 //    on 16 distinct units (all 64 banks) as with the padding.
 //
-// NWN waves along the columns (2 x NWN waves per block): 2 as a rule; 4 with
-// DMA staging puts four waves on each SIMD (two blocks of eight) to hide
-// LDS and barrier latency behind more independent matrix work.
-template <int BM, int BNC, int BKC, bool BF, bool DMA, int NWN = 2>
-__global__ __launch_bounds__(128 * NWN, NWN == 4 ? 2 : ((BM * BNC >= 16384 && BKC >= 32) ? 1 : (BM * BNC >= 16384 || BKC >= 32 ? 2 : 3))) void k_cgemm_split(GemmDesc d) {
-  static_assert(NWN == 2 || (NWN == 4 && DMA), "eight-wave blocks need DMA staging");
-  constexpr int NW = 2 * NWN;  // waves per block
-  using C = SplitCfg<BM, BNC, BKC, NWN>;
+// NWM x NWN waves per block: 2 x 2 as a rule; 2 x 4 with DMA staging puts
+// four waves on each SIMD (two blocks of eight) to hide LDS and barrier
+// latency behind more independent matrix work; wave tiles of four row tiles
+// (1 x 4 waves on 128 x 128, 2 x 2 on 256 x 64) halve the operand-form
+// work per matrix instruction.
+template <int BM, int BNC, int BKC, bool BF, bool DMA, int NWN = 2, int NWM = 2>
+__global__ __launch_bounds__(64 * NWM * NWN, NWM * NWN == 8 ? 2 : ((BM * BNC >= 16384 && BKC >= 32) ? 1 : (BM * BNC >= 16384 || BKC >= 32 ? 2 : 3))) void k_cgemm_split(GemmDesc d) {
+  static_assert((NWN == 2 && NWM == 2) || DMA, "other wave layouts need DMA staging");
+  constexpr int NW = NWM * NWN;  // waves per block
+  using C = SplitCfg<BM, BNC, BKC, NWN, NWM>;
   // LDS rows of U 16-byte units (one unit = 4 complex of hi or lo parts);
   // row r starts at unit U r + r / (16 / U), so that 16 consecutive rows at
   // one group (a read pass) and the 16 / U rows x U groups of a store pass
@@ -624,6 +664,9 @@ __global__ __launch_bounds__(128 * NWN, NWN == 4 ? 2 : ((BM * BNC >= 16384 && BK
   for (int g = 0; g < 4; ++g) pg[g] = pdep64((uint64_t)(8 * g), maskA);
 #pragma unroll
   for (int x = 0; x < C::TM; ++x) pt[x] = pdep64((uint64_t)(32 * x), maskA);
+  // the output's two lowest bits are row bits 0 and 1: a lane's four
+  // accumulators q = 0..3 are four consecutive outputs (16-byte stores)
+  const bool rows4 = (maskA & 3) == 3;
   float vmax = 0.f;
 #pragma unroll
   for (int y = 0; y < C::TN; ++y) {
@@ -631,7 +674,31 @@ __global__ __launch_bounds__(128 * NWN, NWN == 4 ? 2 : ((BM * BNC >= 16384 && BK
 #pragma unroll
     for (int x = 0; x < C::TM; ++x)
 #pragma unroll
-      for (int g = 0; g < 4; ++g)
+      for (int g = 0; g < 4; ++g) {
+        if (rows4) {
+          const uint64_t a0 = pbase | pt[x] | pg[g] | pn;
+          float vr[4], vi[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            vr[q] = are[x][y][4 * g + q] * post;
+            vi[q] = aim[x][y][4 * g + q] * post;
+            vmax = fmaxf(vmax, fmaxf(fabsf(vr[q]), fabsf(vi[q])));
+          }
+          if (d.split_out) {
+            // one split group: 16 bytes of hi words, then 16 bytes of lo words
+            uint32_t hw[4], lw[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) hw[q] = split_pair<BF>(vr[q], vi[q], so, lw[q]);
+            uint4* g4 = reinterpret_cast<uint4*>(Cc) + (a0 >> 2) * 2;
+            g4[0] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+            g4[1] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+          } else {
+            float4* c4 = reinterpret_cast<float4*>(Cc + a0);
+            c4[0] = make_float4(vr[0], vi[0], vr[1], vi[1]);
+            c4[1] = make_float4(vr[2], vi[2], vr[3], vi[3]);
+          }
+          continue;
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           uint64_t addr = pbase | pt[x] | pg[g] | pq[q] | pn;
@@ -642,6 +709,7 @@ __global__ __launch_bounds__(128 * NWN, NWN == 4 ? 2 : ((BM * BNC >= 16384 && BK
           else
             Cc[addr] = make_float2(vr, vi);
         }
+      }
   }
   if (d.scale_c) record_max(d.scale_c + b, vmax);
 }
@@ -668,6 +736,8 @@ const CfgInfo kSplitCfgs[] = {
     {64, 64, 8, "split_dma_64x64x8"},
     // eight waves per block (2 x 4), DMA staging
     {128, 128, 16, "split_dma8w_128x128x16"},
+    // wave tiles of 128 rows x 32 complex columns (DMA staging)
+    {128, 128, 16, "split_dma1x4_128x128x16"}, {256, 64, 16, "split_dma2x2_256x64x16"},
 };
 constexpr int kNumSplit = sizeof(kSplitCfgs) / sizeof(kSplitCfgs[0]);
 
@@ -699,13 +769,14 @@ void run_splitk(const GemmDesc& d, hipStream_t st) {
   hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)(outs / 256)), dim3(256), 0, st, d);
 }
 
-template <int BM, int BNC, int BKC, bool DMA = false, int NWN = 2>
+template <int BM, int BNC, int BKC, bool DMA = false, int NWN = 2, int NWM = 2>
 void run_split(const GemmDesc& d, bool bf, hipStream_t st) {
   int64_t tiles = ((int64_t(1) << d.m) / BM) * ((int64_t(1) << d.n) / BNC) * d.nb;
+  const dim3 block(64 * NWM * NWN);
   if (bf)
-    hipLaunchKernelGGL((k_cgemm_split<BM, BNC, BKC, true, DMA, NWN>), dim3((unsigned)tiles), dim3(128 * NWN), 0, st, d);
+    hipLaunchKernelGGL((k_cgemm_split<BM, BNC, BKC, true, DMA, NWN, NWM>), dim3((unsigned)tiles), block, 0, st, d);
   else
-    hipLaunchKernelGGL((k_cgemm_split<BM, BNC, BKC, false, DMA, NWN>), dim3((unsigned)tiles), dim3(128 * NWN), 0, st, d);
+    hipLaunchKernelGGL((k_cgemm_split<BM, BNC, BKC, false, DMA, NWN, NWM>), dim3((unsigned)tiles), block, 0, st, d);
 }
 
 const CfgInfo& info_of(int cfg, int mode) { return mode == LTN_C64 ? kCfgs[cfg] : kSplitCfgs[cfg]; }
@@ -796,6 +867,8 @@ void launch_cgemm(const GemmDesc& d, int mode, hipStream_t st) {
       case 13: run_split<64, 64, 16, true>(d, bf, st); break;
       case 14: run_split<64, 64, 8, true>(d, bf, st); break;
       case 15: run_split<128, 128, 16, true, 4>(d, bf, st); break;
+      case 16: run_split<128, 128, 16, true, 4, 1>(d, bf, st); break;
+      case 17: run_split<256, 64, 16, true, 2, 2>(d, bf, st); break;
     }
     return;
   }

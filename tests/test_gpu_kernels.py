@@ -13,6 +13,9 @@ from tests.test_gpu_amplitudes import _reduced, _sv
 
 pytestmark = pytest.mark.gpu
 
+# split tile configurations (register-staged 0-9, DMA-staged 10-17)
+N_SPLIT_CFGS = 18
+
 VARIANTS = {
     "narrow_rows_a": [(3, 0, 0, 1)],
     "narrow_rows_b": [(3, 0, 1, 1)],
@@ -22,11 +25,11 @@ VARIANTS = {
     "generic_tk8": [(0, -1, 0, 8)],
     "generic_tk64": [(0, -1, 0, 64)],
     "mfma_c64": [(1, c, s, 1) for s in (0, 1) for c in range(16)],
-    "mfma_split": [(2, c, s, 1) for s in (0, 1) for c in range(16)],
+    "mfma_split": [(2, c, s, 1) for s in (0, 1) for c in range(N_SPLIT_CFGS)],
     # split sum over k for few-output steps (m, n <= 3)
     "split_sum": [(4, 0, 0, 1)],
-    # split tiles staged by global_load_lds (configurations 10-15)
-    "mfma_split_dma": [(2, c, s, 1) for s in (0, 1) for c in range(10, 16)],
+    # split tiles staged by global_load_lds (configurations 10-17)
+    "mfma_split_dma": [(2, c, s, 1) for s in (0, 1) for c in range(10, N_SPLIT_CFGS)],
 }
 
 
@@ -101,7 +104,7 @@ def test_set_step_kernel_rejects_misfits(torch, prepared):
 
 
 def _force_kind(P, plan, k, mode, kind):
-    for cfg in range(16):
+    for cfg in range(N_SPLIT_CFGS):
         for swap in (0, 1):
             try:
                 plan.set_step_kernel(k, mode, kind, cfg, swap, 1)
@@ -247,3 +250,48 @@ def test_narrow_rows_single_step(torch, m, k, n):
             assert err < 1e-5
             runs += 1
     assert runs == 3, "the rows form must fit one operand role"
+
+
+@pytest.mark.parametrize("mode", ["c64", "split_f16", "split_bf16"])
+def test_mfma_output_layouts(torch, mode):
+    """MFMA tiles with the output's lowest bits from either operand: a
+    two-step chain T = A B (contract k), C = T^T D (contract j) whose second
+    step wants j innermost in T, so the first step writes T with its row
+    bits lowest (16-byte epilogue stores) when A holds j (swap 0) and with
+    its column bits lowest when the operands are swapped. Every complex64
+    (and, in the split modes, every split) tile that fits runs the first
+    step; in the split modes the second step is a split tile, so the first
+    writes the split layout in its epilogue. Against the exact product."""
+    import paper_2205_00393_amd as P
+    J, K, M, N = 8, 6, 7, 6
+    rng = np.random.default_rng(4000 + len(mode))
+    cplx = lambda *s: (rng.standard_normal(s) + 1j * rng.standard_normal(s)).astype(np.complex64)
+    a, b, d = cplx(1 << J, 1 << K), cplx(1 << K, 1 << M), cplx(1 << J, 1 << N)
+    ji = list(range(J))
+    ki = list(range(J, J + K))
+    mi = list(range(J + K, J + K + M))
+    ni = list(range(J + K + M, J + K + M + N))
+    net = P.Network.from_arrays([ji + ki, ki + mi, ji + ni], [a, b, d], mi + ni, J + K + M + N)
+    plan = P.Plan(net, [(0, 1), (2, 3)], [])
+    plan.bind(batch=1, budget_bytes=1 << 30)
+    exact = ((a.astype(np.complex128) @ b).T @ d).reshape(-1)
+    st = plan.steps()
+    assert (st[0]["m"], st[0]["k"], st[0]["n"]) in ((J, K, M), (M, K, J))
+    if mode != "c64":
+        assert _force_kind(P, plan, 1, mode, 2), "no split tile fits the second step"
+    kinds = [1] if mode == "c64" else [1, 2]
+    runs = 0
+    for kind in kinds:
+        for cfg in range(N_SPLIT_CFGS):
+            for swap in (0, 1):
+                try:
+                    plan.set_step_kernel(0, mode, kind, cfg, swap, 1)
+                except P.LtnError:
+                    continue
+                out = plan.execute([0], mode=mode)
+                torch.cuda.synchronize()
+                err = rel_l2(out.cpu().numpy(), exact)
+                banner(f"layout chain {mode} kind {kind} cfg {cfg} swap {swap}: rel err {err:.2e}")
+                assert err < (1e-5 if mode == "c64" else 5e-4)
+                runs += 1
+    assert runs >= 4

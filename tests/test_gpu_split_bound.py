@@ -96,7 +96,7 @@ def test_split_gemm_within_analytic_bound(torch, mode, k, wide):
     e_half = _half_only_error(torch, a, b, mode)
 
     ran = 0
-    for cfg in range(16):
+    for cfg in range(18):
         for swap in (0, 1):
             try:
                 plan.set_step_kernel(0, mode, 2, cfg, swap, 1)
