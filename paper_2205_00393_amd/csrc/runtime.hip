@@ -54,6 +54,10 @@ struct ltn_plan_impl {
     int kind = 0, cfg = -1, swap = 0, tk = 1;
   };
   std::vector<Choice> choice[3];
+  // adjoint products (forward-form GEMMs of the gradient sweep) by shape
+  // (m | k << 8 | n << 16): kind 1 = a complex64 tile (cfg, swap) chosen
+  // by ltn_autotune; absent = the fixed rule of enqueue_nt
+  std::map<uint32_t, Choice> adj;
   std::vector<char> needs_grad;
   hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
   hipGraph_t graph_src[3] = {nullptr, nullptr, nullptr};
@@ -873,28 +877,41 @@ extern "C" ltn_status ltn_set_params(ltn_plan* p, const double* d_angles) {
 // X[m 2^k + k] Y[n 2^k + k] over a batch of nb slices, on the complex64
 // MFMA GEMM when a tile fits (either operand role), else the narrow kernel,
 // else the generic kernel.
+uint32_t adj_key(int m, int k, int n) { return (uint32_t)m | (uint32_t)k << 8 | (uint32_t)n << 16; }
+
+static void nt_gemm(ltn_plan* p, const float2* X, int64_t sX, const float2* Y, int64_t sY, float2* C,
+                    int64_t sC, int m, int k, int n, uint64_t cmask, int nb, int sw, int cfg) {
+  const uint64_t full = (m + n) >= 64 ? ~0ull : ((1ull << (m + n)) - 1);
+  GemmDesc d{};
+  d.A = sw ? Y : X;
+  d.B = sw ? X : Y;
+  d.C = C;
+  d.sA = sw ? sY : sX;
+  d.sB = sw ? sX : sY;
+  d.sC = sC;
+  d.m = sw ? n : m;
+  d.n = sw ? m : n;
+  d.k = k;
+  d.cmask = sw ? (~cmask & full) : cmask;
+  d.nb = nb;
+  d.cfg = cfg;
+  launch_cgemm(d, LTN_C64, p->rt->st);
+}
+
 static void enqueue_nt(ltn_plan* p, const float2* X, int64_t sX, const float2* Y, int64_t sY,
                        float2* C, int64_t sC, int m, int k, int n, uint64_t cmask, int nb) {
   auto& r = *p->rt;
   const uint64_t full = (m + n) >= 64 ? ~0ull : ((1ull << (m + n)) - 1);
+  const auto tuned = r.adj.find(adj_key(m, k, n));
+  if (tuned != r.adj.end() && tuned->second.kind == 1) {
+    nt_gemm(p, X, sX, Y, sY, C, sC, m, k, n, cmask, nb, tuned->second.swap, tuned->second.cfg);
+    return;
+  }
   for (int sw = 0; sw < 2; ++sw) {
     const int mm = sw ? n : m, nn = sw ? m : n;
     const int cfg = default_cfg(mm, k, nn, LTN_C64);
     if (cfg >= 0 && mm >= 5 && nn >= 5) {
-      GemmDesc d{};
-      d.A = sw ? Y : X;
-      d.B = sw ? X : Y;
-      d.C = C;
-      d.sA = sw ? sY : sX;
-      d.sB = sw ? sX : sY;
-      d.sC = sC;
-      d.m = mm;
-      d.n = nn;
-      d.k = k;
-      d.cmask = sw ? (~cmask & full) : cmask;
-      d.nb = nb;
-      d.cfg = cfg;
-      launch_cgemm(d, LTN_C64, r.st);
+      nt_gemm(p, X, sX, Y, sY, C, sC, m, k, n, cmask, nb, sw, cfg);
       return;
     }
   }
@@ -1275,6 +1292,106 @@ void drop_graphs(ltn_plan* p) {
   for (int m = 0; m < 3; ++m) r.fseq_valid[m] = false;
 }
 
+// Average duration of `launch` over reps launches (after one untimed launch
+// when warm), with HIP events on the plan's stream.
+template <typename F>
+float time_launch(ltn_plan* p, F&& launch, int reps, bool warm) {
+  auto& r = *p->rt;
+  hipEvent_t a, b;
+  HIPCHECK(hipEventCreate(&a));
+  HIPCHECK(hipEventCreate(&b));
+  if (warm) launch();
+  HIPCHECK(hipEventRecord(a, r.st));
+  for (int i = 0; i < reps; ++i) launch();
+  HIPCHECK(hipEventRecord(b, r.st));
+  HIPCHECK(hipEventSynchronize(b));
+  float ms = 0;
+  HIPCHECK(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  check_launch();
+  return ms / reps;
+}
+
+// Tile choice for the adjoint products of the gradient sweep (plans bound
+// for gradients, complex64): every complex64 tile that fits each product
+// shape in either operand role, against the fixed rule, timed like the
+// forward steps on the gradient scratch buffers (the values do not matter:
+// every product overwrites its output). Cache entries "g0_m_k_n_bB":
+// [1000 + cfg, swap], or [-1, 0] for the fixed rule.
+void tune_adjoint(ltn_plan* p, std::map<std::string, std::pair<int, int>>& cache, bool& dirty) {
+  auto& r = *p->rt;
+  using Choice = ltn_plan_impl::Choice;
+  float2* Xs = reinterpret_cast<float2*>(r.ws + r.lay.gscr_c);
+  float2* Ys = reinterpret_cast<float2*>(r.ws + r.lay.gscr);
+  for (const StepPlan& sp : p->steps) {
+    if (!r.needs_grad[sp.out] || sp.m + sp.n + sp.k <= 16) continue;
+    const TensorPlan &ta = p->tensors[sp.a], &tb = p->tensors[sp.b];
+    const int rc = sp.m + sp.n;
+    for (int which = 0; which < 2; ++which) {
+      if (!r.needs_grad[which ? sp.b : sp.a]) continue;
+      // dA: (m, n, k) with B's layout; dB: (n, m, k) with A's layout
+      const int m = which ? sp.n : sp.m, k = which ? sp.m : sp.n, n = sp.k;
+      const TensorPlan& other = which ? ta : tb;
+      const TensorPlan& self = which ? tb : ta;
+      float2* C = arena_ptr(p, self.gcot);
+      const uint64_t cmask = ((1ull << m) - 1) << n;
+      const uint32_t key = adj_key(m, k, n);
+      if (r.adj.count(key)) continue;
+      std::ostringstream o;
+      o << "g0_" << m << "_" << k << "_" << n << "_b" << r.B;
+      const auto it = cache.find(o.str());
+      Choice pick;  // kind 0: the fixed rule
+      if (it != cache.end()) {
+        if (it->second.first >= 1000) {
+          pick.kind = 1;
+          pick.cfg = it->second.first - 1000;
+          pick.swap = it->second.second;
+        }
+      } else {
+        auto run = [&](const Choice& c) {
+          if (c.kind == 1)
+            nt_gemm(p, Xs, int64_t(1) << rc, Ys, int64_t(1) << other.rank, C, int64_t(1) << self.rank,
+                    m, k, n, cmask, r.B, c.swap, c.cfg);
+          else {
+            r.adj.erase(key);
+            enqueue_nt(p, Xs, int64_t(1) << rc, Ys, int64_t(1) << other.rank, C, int64_t(1) << self.rank,
+                       m, k, n, cmask, r.B);
+          }
+        };
+        std::vector<Choice> cands(1);
+        for (int sw = 0; sw < 2; ++sw)
+          for (int c = 0; c < gemm_config_count(LTN_C64); ++c)
+            if (sw ? gemm_config_fits(c, n, k, m, LTN_C64) : gemm_config_fits(c, m, k, n, LTN_C64)) {
+              Choice ch;
+              ch.kind = 1;
+              ch.cfg = c;
+              ch.swap = sw;
+              cands.push_back(ch);
+            }
+        float best = 1e30f;
+        bool first = true;
+        for (auto& c : cands) {
+          float ms = time_launch(p, [&] { run(c); }, 1, first);
+          first = false;
+          if (ms > 2.0f * best) continue;
+          if (ms < 2.0f)
+            ms = std::min(ms, time_launch(p, [&] { run(c); }, 3, false));
+          else if (ms < 1.05f * best)
+            ms = std::min(ms, time_launch(p, [&] { run(c); }, 1, false));
+          if (ms < best) {
+            best = ms;
+            pick = c;
+          }
+        }
+        cache[o.str()] = pick.kind == 1 ? std::make_pair(1000 + pick.cfg, pick.swap) : std::make_pair(-1, 0);
+        dirty = true;
+      }
+      r.adj[key] = pick;
+    }
+  }
+}
+
 }  // namespace
 
 // Candidates: every MFMA tile configuration that fits the step in either
@@ -1407,6 +1524,7 @@ extern "C" ltn_status ltn_autotune(ltn_plan* p, int32_t mode, const char* cache_
         dirty = true;
       }
     }
+    if (mode == LTN_C64 && r.grad) tune_adjoint(p, cache, dirty);
     if (dirty) write_cache(cache_path, cache);
     HIPCHECK(hipStreamSynchronize(r.st));
   });

@@ -19,12 +19,14 @@ def torch():
     return t
 
 
-def _run(torch, w, batch=0):
+def _run(torch, w, batch=0, tune_cache=None):
     import paper_2205_00393_amd as P
     from paper_2205_00393_amd.autograd import Amplitudes
     pr = P.prepare(w, alphas=(0.5, 1.0), taus=(0.0, 0.3), n_seeds=3)
     plan = pr.plan()
     plan.bind(batch=batch, grad=True, budget_bytes=8 << 30)
+    if tune_cache is not None:
+        plan.autotune("c64", tune_cache)
     ids = [pr.slice_of_bitstring(int(x)) for x in w.bitstrings]
     angles = torch.tensor(w.circuit.angles(), dtype=torch.float64, device="cuda",
                           requires_grad=True)
@@ -68,6 +70,31 @@ def test_rqc20_gradient(torch):
     sub = ref["subset"]
     assert rel_l2(g[sub], ref["finite_diff"]) < 1e-3
     assert rel_l2(g[sub], ref["param_shift"]) < 1e-3
+
+
+def test_rqc20_gradient_autotuned(torch, tmp_path):
+    """The same gradient after ltn_autotune in complex64 on a plan bound
+    for gradients: forward steps and the adjoint products (cache keys
+    g0_m_k_n_bB) take their timed tiles; parity against the oracle's
+    adjoint gradient is unchanged. A second plan reading the written cache
+    reproduces the gradient bit for bit."""
+    import json
+    path = os.path.join(GOLDEN, "rqc20_grad_reference.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden gradient reference not generated")
+    ref = np.load(path)
+    w = make_workload("rqc20_grad")
+    cache = str(tmp_path / "tune.json")
+    banner("rqc20 gradient, autotuned forward and adjoint tiles")
+    psi, loss, g = _run(torch, w, tune_cache=cache)
+    keys = json.load(open(cache))
+    adj = [k for k in keys if k.startswith("g0_")]
+    banner(f"{len(adj)} adjoint product shapes tuned")
+    assert adj, "no adjoint product was tuned"
+    assert rel_l2(psi, ref["amplitudes"]) < 1e-4
+    assert rel_l2(g, ref["grad"]) < 1e-3
+    psi2, loss2, g2 = _run(torch, w, tune_cache=cache)
+    assert np.array_equal(g, g2)
 
 
 def test_gradient_graph_replays_match_eager(torch):
