@@ -30,19 +30,37 @@ __device__ __forceinline__ void record_max(uint32_t* slot, float v) {
   if ((threadIdx.x & 63) == 0) raise_max(slot, v);
 }
 
-// one block per (leaf, slice); threads run over the leaf's elements
-__global__ void k_gather(const GatherDesc* __restrict__ desc, const float2* __restrict__ src,
-                         float2* __restrict__ arena, const uint64_t* __restrict__ ids, int nb,
-                         uint32_t* scales, int bstride) {
-  const GatherDesc& g = desc[blockIdx.x];
+// one block per (chunk of kGatherChunk elements of a leaf, slice): chunks
+// are numbered leaf after leaf (desc[l].chunk0 = first chunk of leaf l);
+// when every leaf is one chunk, block x is leaf x, else a binary search
+// over chunk0 finds the leaf
+__global__ void k_gather(const GatherDesc* __restrict__ desc, int n_leaves, int64_t n_chunks,
+                         const float2* __restrict__ src, float2* __restrict__ arena,
+                         const uint64_t* __restrict__ ids, int nb, uint32_t* scales, int bstride) {
+  const int64_t chunk = blockIdx.x;
+  int leaf = (int)chunk;
+  if (n_chunks != n_leaves) {
+    int lo = 0, hi = n_leaves - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (desc[mid].chunk0 <= chunk)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    leaf = lo;
+  }
+  const GatherDesc& g = desc[leaf];
   int b = blockIdx.y;
   uint64_t s = ids[b];
   int64_t base = g.src_off;
   for (int i = 0; i < g.nsl; ++i) base += (int64_t)((s >> g.sl_bit[i]) & 1) << g.sl_src_bit[i];
   int64_t n = int64_t(1) << g.rank;
   float2* dst = arena + g.dst_off + (int64_t)b * n;
+  const int64_t c0 = (chunk - g.chunk0) * kGatherChunk;
+  const int64_t c1 = c0 + kGatherChunk < n ? c0 + kGatherChunk : n;
   float vmax = 0.f;
-  for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
+  for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
     int64_t o = base;
     for (int j = 0; j < g.rank; ++j) o += ((c >> j) & 1) << g.src_bit[j];
     float2 v = src[o];
@@ -456,12 +474,12 @@ void launch_set_range(uint64_t* d_ids, uint64_t base, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_set_range, dim3((n + 255) / 256), dim3(256), 0, st, d_ids, base, n);
 }
 
-void launch_gather(const GatherDesc* d_desc, int n_leaves, int max_elems, const float2* leafdata,
-                   float2* arena, const uint64_t* ids, int nb, uint32_t* scales, int bstride,
-                   hipStream_t st) {
+void launch_gather(const GatherDesc* d_desc, int n_leaves, int64_t n_chunks, int max_elems,
+                   const float2* leafdata, float2* arena, const uint64_t* ids, int nb, uint32_t* scales,
+                   int bstride, hipStream_t st) {
   int threads = max_elems >= 256 ? 256 : (max_elems >= 64 ? max_elems : 64);
-  hipLaunchKernelGGL(k_gather, dim3(n_leaves, nb), dim3(threads), 0, st, d_desc, leafdata, arena,
-                     ids, nb, scales, bstride);
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)n_chunks, nb), dim3(threads), 0, st, d_desc, n_leaves,
+                     n_chunks, leafdata, arena, ids, nb, scales, bstride);
 }
 
 static SliceOut make_so(const int32_t* sl, const int32_t* ob, int n) {

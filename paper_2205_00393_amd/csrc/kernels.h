@@ -23,8 +23,13 @@ constexpr int kMaxLeafRank = 32;
 
 // Gather of one leaf into its per-slice layout (Sec. 2.1.1: a sliced index
 // takes the value given by the slice id).
+// leaf gather: elements per block (a leaf of 2^rank elements takes
+// ceil(2^rank / kGatherChunk) blocks per slice)
+constexpr int64_t kGatherChunk = 4096;
+
 struct GatherDesc {
   int64_t src_off;   // element offset in the leaf-data area
+  int64_t chunk0;    // first block (chunk) of this leaf in the flattened gather grid
   int64_t tensor;    // tensor id (slot of its per-slice max in split modes)
   int64_t dst_off;   // element offset of slice 0 in the arena
   int32_t rank;      // unsliced rank (dst has 2^rank elements per slice)
@@ -58,9 +63,9 @@ struct GenericDesc {
 
 void launch_set_ids(uint64_t* d_ids, const uint64_t* h_ids, int n, hipStream_t st);
 void launch_set_range(uint64_t* d_ids, uint64_t base, int n, hipStream_t st);
-void launch_gather(const GatherDesc* d_desc, int n_leaves, int max_elems, const float2* leafdata,
-                   float2* arena, const uint64_t* ids, int nb, uint32_t* scales, int bstride,
-                   hipStream_t st);
+void launch_gather(const GatherDesc* d_desc, int n_leaves, int64_t n_chunks, int max_elems,
+                   const float2* leafdata, float2* arena, const uint64_t* ids, int nb, uint32_t* scales,
+                   int bstride, hipStream_t st);
 void launch_reduce(const float2* root, int rank, uint64_t out_mask, const int32_t* sl_bits,
                    const int32_t* out_bits, int n_sl, const uint64_t* ids, int nb, double* out,
                    hipStream_t st);

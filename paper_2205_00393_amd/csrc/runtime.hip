@@ -41,6 +41,7 @@ struct ltn_plan_impl {
   Layout lay{};
   int n_pl = 0;
   int max_leaf_elems = 1;
+  int64_t gather_chunks = 0;  // blocks per slice of the leaf gather
   std::vector<GatherDesc> gd_fwd, gd_grad, gd_gcot;
   std::vector<ParamLeaf> pl;
   std::vector<int32_t> sl_bits, out_bits;
@@ -387,7 +388,7 @@ void enqueue_forward(ltn_plan* p, int nb, bool gradarena, int mode) {
     scales = reinterpret_cast<uint32_t*>(r.ws + r.lay.scales);
     launch_fill_zero(scales, al((size_t)r.B * p->tensors.size() * 4), r.st);
   }
-  launch_gather(gd, (int)p->leaves.size(), r.max_leaf_elems,
+  launch_gather(gd, (int)p->leaves.size(), r.gather_chunks, r.max_leaf_elems,
                 reinterpret_cast<const float2*>(r.ws + r.lay.leafdata), arena_ptr(p, 0),
                 reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids), nb, scales, r.B, r.st);
   if (gradarena && r.gseq_valid) {
@@ -639,6 +640,8 @@ void bind_state(ltn_plan* p, ltn_plan_impl* r, char* d_ws, size_t bytes, int gra
     require(lp.rank_src <= kMaxLeafRank, "leaf rank above 32 is not supported");
     GatherDesc g{};
     g.src_off = lp.src_off;
+    g.chunk0 = r->gather_chunks;
+    r->gather_chunks += ((int64_t(1) << lp.rank) + kGatherChunk - 1) / kGatherChunk;
     g.rank = lp.rank;
     g.nsl = (int32_t)lp.sl_bit.size();
     for (int j = 0; j < lp.rank; ++j) g.src_bit[j] = (int8_t)lp.src_bit[j];
@@ -654,7 +657,7 @@ void bind_state(ltn_plan* p, ltn_plan_impl* r, char* d_ws, size_t bytes, int gra
     r->gd_grad.push_back(g);
     g.dst_off = (int64_t)(t.gcot * (uint64_t)B / 8);
     r->gd_gcot.push_back(g);
-    r->max_leaf_elems = std::max(r->max_leaf_elems, 1 << lp.rank);
+    r->max_leaf_elems = lp.rank >= 30 ? (1 << 30) : std::max(r->max_leaf_elems, 1 << lp.rank);
     if (lp.param >= 0) r->pl.push_back(ParamLeaf{lp.src_off, lp.param, gi});
     ++gi;
   }
@@ -1542,7 +1545,7 @@ extern "C" ltn_status ltn_profile_steps(ltn_plan* p, uint64_t first, int32_t mod
       scales = reinterpret_cast<uint32_t*>(r.ws + r.lay.scales);
       launch_fill_zero(scales, al((size_t)r.B * p->tensors.size() * 4), r.st);
     }
-    launch_gather(gd, (int)p->leaves.size(), r.max_leaf_elems,
+    launch_gather(gd, (int)p->leaves.size(), r.gather_chunks, r.max_leaf_elems,
                   reinterpret_cast<const float2*>(r.ws + r.lay.leafdata), arena_ptr(p, 0),
                   reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids), r.B, scales, r.B, r.st);
     std::vector<hipEvent_t> ev(p->steps.size() + 1);
