@@ -385,7 +385,8 @@ def gradient_leg(torch, P, args):
     w = make_workload("rqc20_grad")
     pr = P.prepare(w, alphas=(0.5, 1.0), taus=(0.0, 0.3), n_seeds=3)
     plan = pr.plan()
-    batch = plan.bind(batch=0, grad=True, budget_bytes=8 << 30)
+    # 32 GiB of the 288 GB hold all 256 bitstring slices in one batch
+    batch = plan.bind(batch=0, grad=True, budget_bytes=32 << 30)
     plan.autotune("c64", args.tune_cache)  # forward steps and the adjoint products
     ids = [pr.slice_of_bitstring(int(x)) for x in w.bitstrings]
     sel = torch.as_tensor(np.asarray(w.bitstrings), device="cuda")
