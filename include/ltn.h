@@ -397,7 +397,10 @@ ltn_status ltn_bind(ltn_plan* plan, void* d_workspace, size_t bytes, int32_t gra
  * batch in ascending position, batches in call order. Asynchronous on the
  * bound stream, except that the first call in a mode after ltn_bind, a
  * kernel choice or a fusion change synchronises it once (the launch
- * descriptors of that mode are uploaded and a graph is captured). Errors:
+ * descriptors of that mode are uploaded and a graph is captured). On a
+ * plan bound with grad != 0, a complex64 call of at most one batch runs in
+ * the gradient arena and its intermediates stay there for a following
+ * ltn_execute_grad on the same ids (see there). Errors:
  * LTN_E_STATE (unbound), LTN_E_INVALID (bad id / mode). */
 ltn_status ltn_execute(ltn_plan* plan, const uint64_t* slice_ids, uint64_t n, int32_t mode,
                        void* d_out);
@@ -449,7 +452,11 @@ ltn_status ltn_set_params(ltn_plan* plan, const double* d_angles);
  * dL/dangle into d_angle_grad (float64 [n_params]); all three are
  * caller-owned device memory. Asynchronous on the bound stream, except that
  * the first call after ltn_bind or a kernel choice change synchronises it
- * once (launch descriptors uploaded, graphs captured). Errors: LTN_E_STATE
+ * once (launch descriptors uploaded, graphs captured). When the previous
+ * call on the plan was a one-batch complex64 ltn_execute of the same id
+ * list (and ltn_set_params was not called since), its intermediates are
+ * still in the gradient arena and the forward is not recomputed; any other
+ * call in between drops them. Errors: LTN_E_STATE
  * if the plan is not bound with grad != 0, LTN_E_INVALID for a bad id or
  * mode, LTN_E_UNSUPPORTED for the split modes (complex64 only). */
 ltn_status ltn_execute_grad(ltn_plan* plan, const uint64_t* slice_ids, uint64_t n, int32_t mode,

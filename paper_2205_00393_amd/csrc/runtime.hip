@@ -72,6 +72,12 @@ struct ltn_plan_impl {
     int step = -1, off = 0, count = 0, tk = 1;
     uint64_t max_outs = 0;
   };
+  // forward kept in the gradient arena by the last ltn_execute (plan bound
+  // for gradients, complex64, one batch) and its slice ids: ltn_execute_grad
+  // on the same ids skips recomputing it; ltn_set_params and every other use
+  // of the arena drop it
+  bool fwd_kept = false;
+  std::vector<uint64_t> fwd_ids;
   bool gseq_valid = false;
   std::vector<GenericDesc> gseq_descs;
   std::vector<GradItem> gseq_fwd, gseq_bwd;
@@ -758,6 +764,8 @@ extern "C" ltn_status ltn_bind(ltn_plan* p, void* d_ws, size_t bytes, int32_t gr
   });
 }
 
+static void build_grad_seq(ltn_plan* p);
+
 static ltn_status execute_impl(ltn_plan* p, const uint64_t* ids, uint64_t begin, uint64_t n,
                                bool range, int32_t mode, void* d_out) {
   return guarded([&] {
@@ -774,6 +782,24 @@ static ltn_status execute_impl(ltn_plan* p, const uint64_t* ids, uint64_t begin,
       if (ns < 64)
         for (uint64_t i = 0; i < n; ++i)
           require(ids[i] < (1ull << ns), "slice id " + std::to_string(ids[i]) + " is not below 2^|S|");
+    }
+    r.fwd_kept = false;
+    if (r.grad && mode == LTN_C64 && n >= 1 && n <= (uint64_t)r.B) {
+      // a plan bound for gradients runs a one-batch forward in its gradient
+      // arena, whose tensors then stay for ltn_execute_grad on the same ids
+      const int nb = (int)n;
+      if (!r.gseq_valid) build_grad_seq(p);
+      set_ids(p, range ? nullptr : ids, begin, nb, range);
+      if (nb == r.B)
+        launch_captured(p, r.ggraph[0], r.ggraph_src[0], [&] { enqueue_forward(p, nb, true, LTN_C64); });
+      else
+        enqueue_forward(p, nb, true, LTN_C64);
+      enqueue_reduce(p, nb, true, reinterpret_cast<double*>(d_out));
+      check_launch();
+      r.fwd_ids.resize(n);
+      for (uint64_t i = 0; i < n; ++i) r.fwd_ids[i] = range ? begin + i : ids[i];
+      r.fwd_kept = true;
+      return;
     }
     for (uint64_t off = 0; off < n; off += (uint64_t)r.B) {
       int nb = (int)std::min<uint64_t>((uint64_t)r.B, n - off);
@@ -867,6 +893,7 @@ extern "C" ltn_status ltn_set_params(ltn_plan* p, const double* d_angles) {
     auto& r = rt(p);
     require(r.n_pl == 0 || d_angles != nullptr, "d_angles is NULL");
     if (r.n_pl == 0) return;
+    r.fwd_kept = false;
     double* ang = reinterpret_cast<double*>(r.ws + r.lay.angles);
     HIPCHECK(hipMemcpyAsync(ang, d_angles, (size_t)p->n_params * sizeof(double),
                             hipMemcpyDeviceToDevice, r.st));
@@ -1189,17 +1216,23 @@ extern "C" ltn_status ltn_execute_grad(ltn_plan* p, const uint64_t* ids, uint64_
       for (uint64_t i = 0; i < n; ++i) require(ids[i] < (1ull << ns), "slice id is not below 2^|S|");
     double* lg = reinterpret_cast<double*>(r.ws + r.lay.leafgrad);
     if (!r.gseq_valid) build_grad_seq(p);
+    // the forward of these very slices (same parameters) is still in the
+    // gradient arena after a one-batch ltn_execute: it is not recomputed
+    const bool kept = r.fwd_kept && n == r.fwd_ids.size() && std::equal(ids, ids + n, r.fwd_ids.begin());
+    r.fwd_kept = false;
     launch_fill_zero(lg, al((size_t)r.n_pl * 64), r.st);
     const uint64_t* dids = reinterpret_cast<const uint64_t*>(r.ws + r.lay.ids);
     // full batches run the recomputed forward and the adjoint sweep from two
     // captured graphs; the cotangent and output pointers stay outside them
     for (uint64_t off = 0; off < n; off += (uint64_t)r.B) {
       int nb = (int)std::min<uint64_t>((uint64_t)r.B, n - off);
-      set_ids(p, ids + off, 0, nb, false);
-      if (nb == r.B)
-        launch_captured(p, r.ggraph[0], r.ggraph_src[0], [&] { enqueue_forward(p, nb, true, LTN_C64); });
-      else
-        enqueue_forward(p, nb, true, LTN_C64);
+      if (!kept) {
+        set_ids(p, ids + off, 0, nb, false);
+        if (nb == r.B)
+          launch_captured(p, r.ggraph[0], r.ggraph_src[0], [&] { enqueue_forward(p, nb, true, LTN_C64); });
+        else
+          enqueue_forward(p, nb, true, LTN_C64);
+      }
       if (d_out) enqueue_reduce(p, nb, true, reinterpret_cast<double*>(d_out));
       const TensorPlan& root = p->tensors[p->root];
       launch_root_cotangent(reinterpret_cast<const double*>(d_cot), root.rank, p->out_mask,
@@ -1292,6 +1325,7 @@ void drop_graphs(ltn_plan* p) {
     r.ggraph_src[m] = nullptr;
   }
   r.gseq_valid = false;  // kernel choices or fusion may have changed
+  r.fwd_kept = false;
   for (int m = 0; m < 3; ++m) r.fseq_valid[m] = false;
 }
 
@@ -1538,6 +1572,7 @@ extern "C" ltn_status ltn_profile_steps(ltn_plan* p, uint64_t first, int32_t mod
     auto& r = rt(p);
     check_mode(mode);
     require(ms_out != nullptr, "ms_out is NULL");
+    r.fwd_kept = false;
     set_ids(p, nullptr, first, r.B, true);
     const GatherDesc* gd = reinterpret_cast<const GatherDesc*>(r.ws + r.lay.gd_fwd);
     uint32_t* scales = nullptr;

@@ -41,6 +41,7 @@ class Plan:
         self._h = h
         self._ws = None
         self.grad_bound = False
+        self.params_token = 0  # counts set_params calls
 
     def __del__(self):
         if getattr(self, "_h", None):
@@ -148,6 +149,7 @@ class Plan:
         a = angles.contiguous()
         L.check(L.lib().ltn_set_params(self._h, C.c_void_p(a.data_ptr())))
         self._angles = a
+        self.params_token += 1
 
     def execute_grad(self, slice_ids, cotangent, out=None, angle_grad=None, mode: str = "c64"):
         torch = _torch()

@@ -97,6 +97,48 @@ def test_rqc20_gradient_autotuned(torch, tmp_path):
     assert np.array_equal(g, g2)
 
 
+def test_gradient_reuses_one_batch_forward(torch):
+    """On a plan bound for gradients with all slices in one batch, the
+    autograd forward (ltn_execute) leaves its intermediates in the gradient
+    arena and the backward does not recompute them. The amplitudes and the
+    gradient must match a plan that recomputes (three batches), and a
+    forward on other slices or new parameters in between must drop the kept
+    intermediates (the gradient is then that of the slices and parameters
+    the backward is asked for)."""
+    import paper_2205_00393_amd as P
+    from paper_2205_00393_amd.autograd import Amplitudes
+    w = _small_workload()
+    pr = P.prepare(w, alphas=(0.5, 1.0), taus=(0.0, 0.3), n_seeds=3)
+    ids = [pr.slice_of_bitstring(int(x)) for x in w.bitstrings]
+    sel = torch.as_tensor(np.asarray(w.bitstrings), device="cuda")
+    a0 = torch.tensor(w.circuit.angles(), dtype=torch.float64, device="cuda")
+    one, three = pr.plan(), pr.plan()
+    assert one.bind(batch=64, grad=True, budget_bytes=1 << 30) >= len(ids)
+    assert three.bind(batch=12, grad=True, budget_bytes=1 << 30) == 12
+
+    def grad(plan, angles, between=None):
+        a = angles.clone().requires_grad_(True)
+        out = Amplitudes.apply(a, plan, ids)
+        if between is not None:
+            between()
+        loss = torch.sum(torch.log(torch.abs(out[sel]) ** 2))
+        loss.backward()
+        torch.cuda.synchronize()
+        return out.detach().cpu().numpy(), a.grad.cpu().numpy()
+
+    o1, g1 = grad(one, a0)
+    o3, g3 = grad(three, a0)
+    banner(f"one-batch reuse vs three batches: amp {rel_l2(o1, o3):.2e}, grad {rel_l2(g1, g3):.2e}")
+    assert rel_l2(o1, o3) < 1e-5 and rel_l2(g1, g3) < 1e-5
+    # other work on the same plan between forward and backward
+    _, g_other = grad(one, a0, between=lambda: one.execute(ids[:5]))
+    assert rel_l2(g_other, g3) < 1e-5
+    a1 = a0 + 0.01
+    _, g_new3 = grad(three, a1)
+    _, g_params = grad(one, a1, between=lambda: one.set_params(a0))
+    assert rel_l2(g_params, g_new3) < 1e-5
+
+
 def test_gradient_graph_replays_match_eager(torch):
     """Full gradient batches run from two captured graphs (recomputed
     forward, adjoint sweep). A plan bound with batch 4 replays them 8 times
