@@ -517,6 +517,15 @@ ltn_status ltn_set_step_kernel(ltn_plan* plan, int32_t step, int32_t mode, int32
 ltn_status ltn_step_kernel(const ltn_plan* plan, int32_t step, int32_t mode, int32_t* kind,
                            int32_t* cfg, int32_t* swap, int32_t* tk);
 
+/* Name of a kernel choice (kind and cfg as in ltn_step_kernel) in a mode,
+ * e.g. "c64_3m_128x64x32": a static string, "?" for a choice that does not
+ * exist. Complex64 tiles named c64_3m_* (kind 1) and splitk_3m_* (kind 5)
+ * form each complex product from three real products (Gauss's method:
+ * Re = ArBr - AiBi, Im = (Ar + Ai)(Br + Bi) - ArBr - AiBi), the others from
+ * the four of the 2x2 real form; the paper does not fix how a complex
+ * product is formed. Host only: needs no plan and no GPU. */
+const char* ltn_kernel_name(int32_t kind, int32_t cfg, int32_t mode);
+
 void ltn_plan_free(ltn_plan* plan);
 const char* ltn_last_error(void);
 const char* ltn_version(void);

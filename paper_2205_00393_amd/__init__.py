@@ -7,8 +7,8 @@ arguments and lends PyTorch device memory and streams.
 from ._lib import LtnError, lib, MODES
 from .network import (Network, greedy_path, tree_costs, tree_stem, stem_profile, slice_finder,
                       path_search, slice_refine, slice_greedy_overhead, tree_reconfigure)
-from .plan import Plan, Prepared, prepare, permute
+from .plan import Plan, Prepared, kernel_name, prepare, permute
 
 __all__ = ["LtnError", "lib", "MODES", "Network", "greedy_path", "tree_costs", "tree_stem",
            "stem_profile", "slice_finder", "path_search", "slice_refine", "slice_greedy_overhead",
-           "tree_reconfigure", "Plan", "Prepared", "prepare", "permute"]
+           "tree_reconfigure", "Plan", "Prepared", "kernel_name", "prepare", "permute"]

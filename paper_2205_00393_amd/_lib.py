@@ -118,13 +118,14 @@ SIGNATURES = {
     "ltn_set_fusion": [P, I32],
     "ltn_set_step_kernel": [P, I32, I32, I32, I32, I32, I32],
     "ltn_step_kernel": [P, I32, I32, I32P, I32P, I32P, I32P],
+    "ltn_kernel_name": [I32, I32, I32],
     "ltn_permute": [P, P, I32, I32P, C.c_int64, P],
     "ltn_plan_free": [P],
     "ltn_last_error": [],
     "ltn_version": [],
 }
 VOID_RET = {"ltn_netbuf_free", "ltn_plan_free"}
-STR_RET = {"ltn_last_error", "ltn_version"}
+STR_RET = {"ltn_last_error", "ltn_version", "ltn_kernel_name"}
 
 _lib = None
 

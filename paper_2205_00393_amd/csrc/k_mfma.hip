@@ -134,13 +134,15 @@ __device__ __forceinline__ float split_out_scale(const GemmDesc& d, int64_t b, i
 }
 
 // NWN waves along the columns (2: waves 2 x 2; 1: waves 4 x 1, for tiles
-// of 16 complex columns)
-template <int BM, int BNC, int BKC, int NWN = 2>
+// of 16 complex columns). G3: the three-product form, whose MFMA columns
+// are complex outputs (32 per tile) instead of real ones (16 complex).
+template <int BM, int BNC, int BKC, int NWN = 2, bool G3 = false>
 struct Cfg {
   static constexpr int WM = BM / (4 / NWN);  // rows per wave
   static constexpr int TM = WM / 32;         // 32-row MFMA tiles per wave
   static constexpr int WNC = BNC / NWN;      // complex columns per wave
-  static constexpr int TN = (2 * WNC) / 32;  // 32-real-column MFMA tiles per wave
+  static constexpr int CPT = G3 ? 32 : 16;   // complex columns per MFMA tile
+  static constexpr int TN = WNC / CPT;       // MFMA column tiles per wave
   static constexpr int LDA = BKC + 1;        // padded row length (complex)
   static constexpr int CHA = BM * BKC / 2;   // float4 chunks of the A tile
   static constexpr int CHB = BNC * BKC / 2;
@@ -153,9 +155,27 @@ struct Cfg {
 // consecutive k) for tile w % (tiles * nb), and writes its FP32 partial of
 // C to part in plain row-major order ([b][chunk][row][column]); the split
 // layout and the per-slice maxima are left to the pass that adds the chunks.
-template <int BM, int BNC, int BKC, int NWN = 2, bool SPLITK = false>
-__global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
-  using C = Cfg<BM, BNC, BKC, NWN>;
+//
+// G3: the complex product by three real products (Gauss's method; its
+// rounding for matrix products is analysed by Higham, SIAM J. Matrix Anal.
+// Appl. 13, 1992):
+//   P1 = Ar Br^T,  P2 = Ai Bi^T,  P3 = (Ar + Ai)(Br + Bi)^T,
+//   Re C = P1 - P2,  Im C = P3 - P1 - P2,
+// three real GEMMs of M x N x K, i.e. 3 real MACs per complex MAC instead
+// of the 4 of the 2x2 real form. The real part is formed exactly as in the
+// direct form; the imaginary part's error bound grows from terms in
+// |Ar||Bi| + |Ai||Br| to terms in (|Ar| + |Ai|)(|Br| + |Bi|), at most
+// about twice as large. Lane l's MFMA operand is row l % 32, k l / 32 of A
+// and column l % 32 of B, so one 8-byte LDS read of a complex element of
+// each gives the operands of P1 and P2, and their sums those of P3; the
+// accumulators of a lane hold whole complex outputs.
+//
+// MINW: waves per SIMD the registers must allow (1: the compiler's choice;
+// the three-product 128 x 64 x 16 tile fits three with its accumulators in
+// VGPRs and no spills, against two when left to the compiler).
+template <int BM, int BNC, int BKC, int NWN = 2, bool SPLITK = false, bool G3 = false, int MINW = 1>
+__global__ __launch_bounds__(256, MINW) void k_cgemm_c64(GemmDesc d) {
+  using C = Cfg<BM, BNC, BKC, NWN, G3>;
   __shared__ float2 As[BM * C::LDA];
   __shared__ float2 Bs[BNC * C::LDA];
 
@@ -181,13 +201,24 @@ __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
   const int wm = wave / NWN, wn = wave % NWN;
   const int h = lane >> 5, i = lane & 31;
 
-  floatx16 acc[C::TM][C::TN];
+  // G3: acc = P1, acc2 = P2, acc3 = P3 (unused by the direct form)
+  constexpr int T2 = G3 ? C::TM : 1, U2 = G3 ? C::TN : 1;
+  floatx16 acc[C::TM][C::TN], acc2[T2][U2], acc3[T2][U2];
 #pragma unroll
   for (int x = 0; x < C::TM; ++x)
 #pragma unroll
     for (int y = 0; y < C::TN; ++y)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[x][y][v] = 0.f;
+#pragma unroll
+  for (int x = 0; x < T2; ++x)
+#pragma unroll
+    for (int y = 0; y < U2; ++y)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        acc2[x][y][v] = 0.f;
+        acc3[x][y][v] = 0.f;
+      }
 
   float4 ra[C::RA], rb[C::RB];
   auto load = [&](int64_t k0) {
@@ -230,10 +261,11 @@ __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
   };
 
   const int arow0 = wm * C::WM + i;
-  // B column of this lane in MFMA tile y: real column 32 y + i of the wave
-  // = complex column (32 y + i) / 2, part i & 1 (0: re, 1: im)
-  const int bcol0 = wn * C::WNC + (i >> 1);
-  const bool im_col = (i & 1) != 0;
+  // B column of this lane in MFMA tile y: direct form: real column 32 y + i
+  // of the wave = complex column (32 y + i) / 2, part i & 1 (0: re, 1: im);
+  // G3: complex column 32 y + i
+  const int bcol0 = wn * C::WNC + (G3 ? i : (i >> 1));
+  const bool im_col = !G3 && (i & 1) != 0;
 
   load(0);
   for (int64_t k0 = 0; k0 < KL; k0 += BKC) {
@@ -247,15 +279,31 @@ __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
 #pragma unroll
       for (int x = 0; x < C::TM; ++x) av[x] = As[(arow0 + 32 * x) * C::LDA + kp + h];
 #pragma unroll
-      for (int y = 0; y < C::TN; ++y) bv[y] = Bs[(bcol0 + 16 * y) * C::LDA + kp + h];
+      for (int y = 0; y < C::TN; ++y) bv[y] = Bs[(bcol0 + C::CPT * y) * C::LDA + kp + h];
+      if constexpr (G3) {
+        float as[C::TM];
 #pragma unroll
-      for (int y = 0; y < C::TN; ++y) {
-        float b1 = im_col ? bv[y].y : bv[y].x;   // pairs with Re a
-        float b2 = im_col ? bv[y].x : -bv[y].y;  // pairs with Im a
+        for (int x = 0; x < C::TM; ++x) as[x] = av[x].x + av[x].y;
 #pragma unroll
-        for (int x = 0; x < C::TM; ++x) {
-          acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[x].x, b1, acc[x][y], 0, 0, 0);
-          acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[x].y, b2, acc[x][y], 0, 0, 0);
+        for (int y = 0; y < C::TN; ++y) {
+          const float bs = bv[y].x + bv[y].y;
+#pragma unroll
+          for (int x = 0; x < C::TM; ++x) {
+            acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[x].x, bv[y].x, acc[x][y], 0, 0, 0);
+            acc2[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[x].y, bv[y].y, acc2[x][y], 0, 0, 0);
+            acc3[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[x], bs, acc3[x][y], 0, 0, 0);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int y = 0; y < C::TN; ++y) {
+          float b1 = im_col ? bv[y].y : bv[y].x;   // pairs with Re a
+          float b2 = im_col ? bv[y].x : -bv[y].y;  // pairs with Im a
+#pragma unroll
+          for (int x = 0; x < C::TM; ++x) {
+            acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[x].x, b1, acc[x][y], 0, 0, 0);
+            acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[x].y, b2, acc[x][y], 0, 0, 0);
+          }
         }
       }
     }
@@ -280,12 +328,53 @@ __global__ __launch_bounds__(256) void k_cgemm_c64(GemmDesc d) {
   float vmax = 0.f;
 #pragma unroll
   for (int y = 0; y < C::TN; ++y) {
-    uint64_t ncol = (uint64_t)(bn * BNC + bcol0 + 16 * y);
+    uint64_t ncol = (uint64_t)(bn * BNC + bcol0 + C::CPT * y);
     uint64_t pn = pdep64(ncol, maskB);
 #pragma unroll
     for (int x = 0; x < C::TM; ++x)
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
+        if constexpr (G3) {
+          // whole complex outputs: Re = P1 - P2, Im = P3 - P1 - P2
+          float vr[4], vi[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float p1 = acc[x][y][4 * g + q], p2 = acc2[x][y][4 * g + q];
+            vr[q] = p1 - p2;
+            vi[q] = acc3[x][y][4 * g + q] - p1 - p2;
+            vmax = fmaxf(vmax, fmaxf(fabsf(vr[q]), fabsf(vi[q])));
+          }
+          if (rows4) {
+            const uint64_t a0 = pbase | pt[x] | pg[g] | pn;
+            if (!SPLITK && d.split_out) {
+              // one split group: 16 bytes of hi words, then 16 bytes of lo words
+              uint32_t hw[4], lw[4];
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+                hw[q] = d.split_out == 1 ? split_pair<true>(vr[q], vi[q], 1.f, lw[q])
+                                         : split_pair<false>(vr[q], vi[q], so, lw[q]);
+              uint4* g4 = reinterpret_cast<uint4*>(Cw) + (a0 >> 2) * 2;
+              g4[0] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+              g4[1] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+            } else {
+              float4* c4 = reinterpret_cast<float4*>(Cf + 2 * a0);
+              c4[0] = make_float4(vr[0], vi[0], vr[1], vi[1]);
+              c4[1] = make_float4(vr[2], vi[2], vr[3], vi[3]);
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const uint64_t addr = pbase | pt[x] | pg[g] | pq[q] | pn;
+              if (!SPLITK && d.split_out == 1)
+                store_split<true>(Cw, addr, vr[q], vi[q], 1.f);
+              else if (!SPLITK && d.split_out)
+                store_split<false>(Cw, addr, vr[q], vi[q], so);
+              else
+                reinterpret_cast<float2*>(Cf)[addr] = make_float2(vr[q], vi[q]);
+            }
+          }
+          continue;
+        }
         if (rows4) {
           const uint64_t a0 = pbase | pt[x] | pg[g] | pn;
           float v[4];
@@ -723,6 +812,10 @@ const CfgInfo kCfgs[] = {
     {64, 32, 16, "c64_64x32x16"},   {128, 64, 8, "c64_128x64x8"},  {64, 32, 8, "c64_64x32x8"},
     {64, 32, 4, "c64_64x32x4"},     {64, 32, 2, "c64_64x32x2"},    {256, 64, 16, "c64_256x64x16"},
     {128, 128, 16, "c64_128x128x16"},
+    // three real products per complex product (configurations 10-15)
+    {128, 64, 16, "c64_3m_128x64x16"}, {128, 128, 16, "c64_3m_128x128x16"},
+    {256, 64, 16, "c64_3m_256x64x16"}, {64, 64, 16, "c64_3m_64x64x16"},
+    {128, 64, 32, "c64_3m_128x64x32"}, {128, 32, 16, "c64_3m_128x32x16"},
 };
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 const CfgInfo kSplitCfgs[] = {
@@ -741,13 +834,14 @@ const CfgInfo kSplitCfgs[] = {
 };
 constexpr int kNumSplit = sizeof(kSplitCfgs) / sizeof(kSplitCfgs[0]);
 
-template <int BM, int BNC, int BKC>
+template <int BM, int BNC, int BKC, int NWN = 2, bool G3 = false, int MINW = 1>
 void run(const GemmDesc& d, hipStream_t st) {
   int64_t tiles = ((int64_t(1) << d.m) / BM) * ((int64_t(1) << d.n) / BNC) * d.nb;
-  hipLaunchKernelGGL((k_cgemm_c64<BM, BNC, BKC>), dim3((unsigned)tiles), dim3(256), 0, st, d);
+  hipLaunchKernelGGL((k_cgemm_c64<BM, BNC, BKC, NWN, false, G3, MINW>), dim3((unsigned)tiles), dim3(256), 0, st, d);
 }
 
-// Split-K tiles: waves 4 x 1 for 16 and 32 complex columns, 2 x 2 otherwise.
+// Split-K tiles: waves 4 x 1 for 16 and 32 complex columns, 2 x 2 otherwise;
+// configurations 4 and 5 take the three-product form.
 struct SplitKCfg {
   int bm, bnc, bkc;
   const char* name;
@@ -757,14 +851,16 @@ const SplitKCfg kSplitKCfgs[] = {
     {256, 16, 16, "splitk_256x16x16"},
     {128, 32, 16, "splitk_128x32x16"},
     {128, 64, 16, "splitk_128x64x16"},
+    {128, 64, 16, "splitk_3m_128x64x16"},
+    {128, 32, 16, "splitk_3m_128x32x16"},
 };
 constexpr int kNumSplitK = sizeof(kSplitKCfgs) / sizeof(kSplitKCfgs[0]);
 
-template <int BM, int BNC, int BKC, int NWN>
+template <int BM, int BNC, int BKC, int NWN, bool G3 = false, int MINW = 1>
 void run_splitk(const GemmDesc& d, hipStream_t st) {
   const int64_t chunks = int64_t(1) << (d.k - d.kc_bits);
   const int64_t blocks = ((int64_t(1) << d.m) / BM) * ((int64_t(1) << d.n) / BNC) * d.nb * chunks;
-  hipLaunchKernelGGL((k_cgemm_c64<BM, BNC, BKC, NWN, true>), dim3((unsigned)blocks), dim3(256), 0, st, d);
+  hipLaunchKernelGGL((k_cgemm_c64<BM, BNC, BKC, NWN, true, G3, MINW>), dim3((unsigned)blocks), dim3(256), 0, st, d);
   const int64_t outs = (int64_t(1) << (d.m + d.n)) * d.nb;
   hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)(outs / 256)), dim3(256), 0, st, d);
 }
@@ -830,6 +926,8 @@ void launch_cgemm_splitk(const GemmDesc& d0, hipStream_t st) {
     case 1: run_splitk<256, 16, 16, 1>(d, st); break;
     case 2: run_splitk<128, 32, 16, 1>(d, st); break;
     case 3: run_splitk<128, 64, 16, 2>(d, st); break;
+    case 4: run_splitk<128, 64, 16, 2, true, 3>(d, st); break;
+    case 5: run_splitk<128, 32, 16, 1, true>(d, st); break;
   }
 }
 
@@ -883,6 +981,12 @@ void launch_cgemm(const GemmDesc& d, int mode, hipStream_t st) {
     case 7: run<64, 32, 2>(d, st); break;
     case 8: run<256, 64, 16>(d, st); break;
     case 9: run<128, 128, 16>(d, st); break;
+    case 10: run<128, 64, 16, 2, true, 3>(d, st); break;
+    case 11: run<128, 128, 16, 2, true>(d, st); break;
+    case 12: run<256, 64, 16, 2, true>(d, st); break;
+    case 13: run<64, 64, 16, 2, true>(d, st); break;
+    case 14: run<128, 64, 32, 2, true>(d, st); break;
+    case 15: run<128, 32, 16, 1, true>(d, st); break;
   }
 }
 

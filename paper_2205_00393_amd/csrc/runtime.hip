@@ -159,9 +159,16 @@ float2* arena_ptr(ltn_plan* p, uint64_t off_bytes) {
   return reinterpret_cast<float2*>(r.ws + r.lay.arena + off_bytes * (uint64_t)r.B);
 }
 
+// Untuned complex64 tiles: the three-product tiles first, then the direct
+// tiles 0-7 (sums shorter than 16); split modes: in order.
 int default_cfg(int m, int k, int n, int mode) {
-  int lim = mode == LTN_C64 ? 8 : gemm_config_count(mode);
-  for (int c = 0; c < lim; ++c)
+  static const int c64_order[] = {10, 15, 13, 0, 1, 2, 3, 4, 5, 6, 7};
+  if (mode == LTN_C64) {
+    for (int c : c64_order)
+      if (gemm_config_fits(c, m, k, n, mode)) return c;
+    return -1;
+  }
+  for (int c = 0; c < gemm_config_count(mode); ++c)
     if (gemm_config_fits(c, m, k, n, mode)) return c;
   return -1;
 }
@@ -1661,6 +1668,19 @@ extern "C" ltn_status ltn_step_kernel(const ltn_plan* p, int32_t step, int32_t m
     if (swap) *swap = c.swap;
     if (tk) *tk = c.tk;
   });
+}
+
+extern "C" const char* ltn_kernel_name(int32_t kind, int32_t cfg, int32_t mode) {
+  if (mode < LTN_C64 || mode > LTN_SPLIT_BF16) return "?";
+  switch (kind) {
+    case 0: return "generic";
+    case 1: return gemm_config_name(cfg, LTN_C64);
+    case 2: return mode == LTN_C64 ? "?" : gemm_config_name(cfg, mode);
+    case 3: return cfg == 0 ? "narrow_tile" : (cfg == 1 ? "narrow_rows" : "?");
+    case 4: return cfg == 0 ? "split_sum" : "?";
+    case 5: return splitk_config_name(cfg);
+  }
+  return "?";
 }
 
 // Tile plan of a bit permutation (see k_permute): the tile holds the lowest

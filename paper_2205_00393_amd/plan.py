@@ -181,11 +181,21 @@ class Plan:
 
     def step_kernel(self, k: int, mode: str = "c64"):
         """(kind, cfg, swap, tk): kind 0 generic, 1 complex64 MFMA, 2 split MFMA,
-        3 narrow, 4 split sum."""
+        3 narrow, 4 split sum, 5 split-K complex64 MFMA."""
         kind, cfg, sw, tk = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         L.check(L.lib().ltn_step_kernel(self._h, k, L.MODES[mode], C.byref(kind), C.byref(cfg),
                                         C.byref(sw), C.byref(tk)))
         return kind.value, cfg.value, sw.value, tk.value
+
+    def step_kernel_name(self, k: int, mode: str = "c64") -> str:
+        """Name of the kernel choice of step k (ltn_kernel_name)."""
+        kind, cfg, _, _ = self.step_kernel(k, mode)
+        return kernel_name(kind, cfg, mode)
+
+
+def kernel_name(kind: int, cfg: int, mode: str = "c64") -> str:
+    """Name of a kernel choice (ltn_kernel_name); "?" if there is none."""
+    return L.lib().ltn_kernel_name(kind, cfg, L.MODES[mode]).decode()
 
 
 @dataclass

@@ -51,3 +51,24 @@ def test_permute_argument_checks_without_gpu():
     assert "aligned" in L.ltn_last_error().decode()
     assert L.ltn_permute(C.c_void_p(4096), C.c_void_p(8200), 3, perm, 1, None) == -1
     assert "aligned" in L.ltn_last_error().decode()
+
+
+def test_kernel_names_without_gpu():
+    """Kernel choices are named on the host: the complex64 tiles 10-15 and
+    split-K tiles 4-5 are the three-product form (c64_3m_*, splitk_3m_*),
+    tiles 0-9 and split-K 0-3 the direct form; a split kind has no name in
+    complex64 mode and choices past the tables are "?"."""
+    import paper_2205_00393_amd as P
+    direct = [P.kernel_name(1, c) for c in range(10)]
+    three = [P.kernel_name(1, c) for c in range(10, 16)]
+    assert all(n.startswith("c64_") and "_3m_" not in n for n in direct)
+    assert all(n.startswith("c64_3m_") for n in three)
+    assert len(set(direct + three)) == 16
+    assert P.kernel_name(1, 16) == "?" and P.kernel_name(1, -1) == "?"
+    assert [P.kernel_name(5, c) for c in range(6)][3:] == \
+        ["splitk_128x64x16", "splitk_3m_128x64x16", "splitk_3m_128x32x16"]
+    assert P.kernel_name(5, 6) == "?"
+    assert P.kernel_name(2, 0, "c64") == "?"
+    assert P.kernel_name(2, 16, "split_bf16") == "split_dma1x4_128x128x16"
+    assert P.kernel_name(3, 1) == "narrow_rows" and P.kernel_name(4, 0) == "split_sum"
+    assert P.kernel_name(0, -1) == "generic" and P.kernel_name(9, 0) == "?"

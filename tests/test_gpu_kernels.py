@@ -15,6 +15,8 @@ pytestmark = pytest.mark.gpu
 
 # split tile configurations (register-staged 0-9, DMA-staged 10-17)
 N_SPLIT_CFGS = 18
+# complex64 tile configurations (direct form 0-9, three-product form 10-15)
+N_C64_CFGS = 16
 
 VARIANTS = {
     "narrow_rows_a": [(3, 0, 0, 1)],
@@ -24,7 +26,9 @@ VARIANTS = {
     "generic_tk1": [(0, -1, 0, 1)],
     "generic_tk8": [(0, -1, 0, 8)],
     "generic_tk64": [(0, -1, 0, 64)],
-    "mfma_c64": [(1, c, s, 1) for s in (0, 1) for c in range(16)],
+    "mfma_c64": [(1, c, s, 1) for s in (0, 1) for c in range(10)],
+    # complex64 tiles with three real products per complex product (10-15)
+    "mfma_c64_3m": [(1, c, s, 1) for s in (0, 1) for c in range(10, N_C64_CFGS)],
     "mfma_split": [(2, c, s, 1) for s in (0, 1) for c in range(N_SPLIT_CFGS)],
     # split sum over k for few-output steps (m, n <= 3)
     "split_sum": [(4, 0, 0, 1)],
@@ -190,8 +194,9 @@ def test_split_sum_single_step(torch, m, k, n):
 def test_splitk_single_step(torch, m, k, n):
     """The split-K complex64 MFMA GEMM (kind 5) alone on one-step networks:
     C = A B with 2^m x 2^k and 2^k x 2^n complex64 operands, every tile
-    configuration in both operand roles where it fits (from 2 to 256 chunks
-    of the sum), in every mode, against the exact product."""
+    configuration (direct and three-product form) in both operand roles
+    where it fits (from 2 to 256 chunks of the sum), in every mode, against
+    the exact product."""
     import paper_2205_00393_amd as P
     rng = np.random.default_rng(2000 + 100 * m + 10 * n + k)
     M, K, N = 1 << m, 1 << k, 1 << n
@@ -205,7 +210,7 @@ def test_splitk_single_step(torch, m, k, n):
     runs = 0
     for mode in ("c64", "split_f16", "split_bf16"):
         for swap in (0, 1):
-            for cfg in range(4):
+            for cfg in range(6):
                 try:
                     plan.set_step_kernel(0, mode, 5, cfg, swap, 1)
                 except P.LtnError:
@@ -282,7 +287,7 @@ def test_mfma_output_layouts(torch, mode):
     kinds = [1] if mode == "c64" else [1, 2]
     runs = 0
     for kind in kinds:
-        for cfg in range(N_SPLIT_CFGS):
+        for cfg in range(N_C64_CFGS if kind == 1 else N_SPLIT_CFGS):
             for swap in (0, 1):
                 try:
                     plan.set_step_kernel(0, mode, kind, cfg, swap, 1)
