@@ -258,9 +258,15 @@ def time_plan(torch, P, pr, workload, modes, args, tag, fuse_rank=0, golden=None
         # flops per complex MAC: 8 on the direct complex64 tiles, 6 on the
         # three-product ones (c64_3m_*, splitk_3m_*), 24 on the split tiles
         # (three fp16/bf16 products of the 2x2 real form)
+        # A matrix-core step is GEMM-bound when its executed flops per
+        # algorithmic byte reach the ridge (matrix peak / 8 TB/s HBM);
+        # steps below it (short sums, large outputs) are bound by HBM.
         fam = {"k_cgemm_c64": (1, 5), "k_cgemm_split": (2,), "k_narrow": (3,)}
         kern = {name: {"launches": 0, "flops_per_batch": 0.0, "exec_flops_per_batch": 0.0,
                        "alg_bytes_per_batch": 0.0, "ms_per_batch": 0.0, "tiles": {}} for name in fam}
+        for name in ("k_cgemm_c64", "k_cgemm_split"):
+            kern[name]["steps"] = []
+            kern[name]["gemm_bound"] = {"launches": 0, "exec_flops_per_batch": 0.0, "ms_per_batch": 0.0}
         mf_flops, mf_ms, mf_launch, split_flops = 0.0, 0.0, 0, 0.0
         for k, st in enumerate(steps):
             kind, _, _, _ = plan.step_kernel(k, mode)
@@ -272,9 +278,19 @@ def time_plan(torch, P, pr, workload, modes, args, tag, fuse_rank=0, golden=None
                     e["flops_per_batch"] += f
                     tile = plan.step_kernel_name(k, mode)
                     e["tiles"][tile] = e["tiles"].get(tile, 0) + 1
-                    e["exec_flops_per_batch"] += f * (3.0 if kind == 2 else (0.75 if "_3m_" in tile else 1.0))
-                    e["alg_bytes_per_batch"] += 8.0 * ((1 << (st["m"] + st["k"])) + (1 << (st["n"] + st["k"])) +
-                                                       (1 << (st["m"] + st["n"]))) * batch
+                    fx = f * (3.0 if kind == 2 else (0.75 if "_3m_" in tile else 1.0))
+                    by = 8.0 * ((1 << (st["m"] + st["k"])) + (1 << (st["n"] + st["k"])) + (1 << (st["m"] + st["n"]))) * batch
+                    e["exec_flops_per_batch"] += fx
+                    e["alg_bytes_per_batch"] += by
+                    if "steps" in e:
+                        pk = PEAK_F16_MFMA_TFLOPS if kind == 2 else PEAK_FP32_MFMA_TFLOPS
+                        bound = fx / by >= pk / PEAK_HBM_GBS * 1e3
+                        e["steps"].append([k, st["m"], st["k"], st["n"], tile, round(float(ms[k]), 4), bound])
+                        if bound:
+                            g = e["gemm_bound"]
+                            g["launches"] += 1
+                            g["exec_flops_per_batch"] += fx
+                            g["ms_per_batch"] += float(ms[k])
                     e["ms_per_batch"] += ms[k]
                     if name == "k_narrow":
                         continue
@@ -286,6 +302,9 @@ def time_plan(torch, P, pr, workload, modes, args, tag, fuse_rank=0, golden=None
         for e in kern.values():
             e["alg_tflops"] = e["flops_per_batch"] / (e["ms_per_batch"] * 1e-3) / 1e12 if e["ms_per_batch"] > 0 else 0.0
             e["exec_tflops"] = e["exec_flops_per_batch"] / (e["ms_per_batch"] * 1e-3) / 1e12 if e["ms_per_batch"] > 0 else 0.0
+            if "gemm_bound" in e:
+                g = e["gemm_bound"]
+                g["exec_tflops"] = g["exec_flops_per_batch"] / (g["ms_per_batch"] * 1e-3) / 1e12 if g["ms_per_batch"] > 0 else 0.0
             e["alg_gbs"] = e["alg_bytes_per_batch"] / (e["ms_per_batch"] * 1e-3) / 1e9 if e["ms_per_batch"] > 0 else 0.0
         res["kernels"] = kern
         res["mfma_ms_per_batch"] = mf_ms
@@ -336,6 +355,11 @@ def roofline_of(workload, mode, r):
             "executed_frac": round(e["exec_tflops"] / peak, 4),
             "executed_flops_per_complex_mac": "6 on c64_3m/splitk_3m tiles, 8 on direct complex64 tiles"
             if mode == "c64" else "24 (three fp16/bf16 products of the 2x2 real form)",
+            "gemm_bound_steps": {"launches": e["gemm_bound"]["launches"],
+                                 "share_of_kernel_time": round(e["gemm_bound"]["ms_per_batch"] / e["ms_per_batch"], 4)
+                                 if e["ms_per_batch"] > 0 else 0.0,
+                                 "executed": round(e["gemm_bound"]["exec_tflops"], 3),
+                                 "executed_frac": round(e["gemm_bound"]["exec_tflops"] / peak, 4)},
             "launches_per_batch": e["launches"],
             "share_of_step_time": round(e["ms_per_batch"] / r["step_ms_per_batch"], 4)}
 
@@ -562,6 +586,15 @@ def summarize_main(argv):
             tf = n_inst * fpi / (sum(md_durs) * 1e-9) / 1e12
             mc.update(duration_ms_total=sum(md_durs) / 1e6, executed_tflops_from_counters=tf,
                       frac_of_peak_from_counters=tf / peak)
+            # the GEMM-bound steps: the kept dispatches are whole batches, a
+            # batch launching the family's steps in step order
+            if e.get("steps") and len(e["steps"]) == launches:
+                vals = [inst[key] for key in sorted(inst)]
+                sel = [j for j in range(len(vals)) if e["steps"][j % launches][6]]
+                if sel:
+                    gtf = sum(vals[j] for j in sel) * fpi / (sum(md_durs[j] for j in sel) * 1e-9) / 1e12
+                    mc.update(gemm_bound_dispatches=len(sel), gemm_bound_executed_tflops_from_counters=gtf,
+                              gemm_bound_frac_of_peak_from_counters=gtf / peak)
         rec["mfma_counters"] = mc
     if a.bound == "mfma":
         first = (f"* {a.kernel}: {launches} launches per batch, average {avg_ms:.3f} ms per launch "
@@ -583,13 +616,26 @@ def summarize_main(argv):
            f"* {src_name} sha256 at measurement: `{rec['source_sha256']}`"]
     if e.get("tiles"):
         md.append("* Tiles per batch: " + ", ".join(f"{t} x {c}" for t, c in sorted(e["tiles"].items())) + ".")
+    if e.get("gemm_bound") and e["gemm_bound"]["launches"]:
+        g = e["gemm_bound"]
+        rec["gemm_bound"] = {"launches_per_batch": g["launches"], "share_of_kernel_time": g["ms_per_batch"] / e["ms_per_batch"],
+                             "executed_tflops_hip_events": g["exec_tflops"], "frac_of_peak": g["exec_tflops"] / peak}
+        md.append(f"* GEMM-bound steps (executed flops per algorithmic byte at or above the ridge, {peak} TFLOP/s "
+                  f"/ {PEAK_HBM_GBS:.0f} GB/s): {g['launches']} of {launches} launches per batch, "
+                  f"{100 * g['ms_per_batch'] / e['ms_per_batch']:.1f} % of the kernel's time, executed "
+                  f"{g['exec_tflops']:.1f} TFLOP/s = {100 * g['exec_tflops'] / peak:.1f} % of peak (HIP events in the "
+                  f"bench run); the other steps are bound by HBM.")
     if "mfma_counters" in rec and "executed_tflops_from_counters" in rec["mfma_counters"]:
         mc = rec["mfma_counters"]
         md.append(f"* MFMA instruction counters: {mc['mfma_instructions']:.4e} instructions x "
                   f"{mc['flops_per_instruction']} flops in {mc['duration_ms_total']:.1f} ms of kernel time "
                   f"({mc['dispatches']} dispatches; counter runs serialise kernels) = "
                   f"{mc['executed_tflops_from_counters']:.1f} TFLOP/s = "
-                  f"{100 * mc['frac_of_peak_from_counters']:.1f} % of peak.")
+                  f"{100 * mc['frac_of_peak_from_counters']:.1f} % of peak"
+                  + (f"; GEMM-bound steps alone ({mc['gemm_bound_dispatches']} dispatches) "
+                     f"{mc['gemm_bound_executed_tflops_from_counters']:.1f} TFLOP/s = "
+                     f"{100 * mc['gemm_bound_frac_of_peak_from_counters']:.1f} %."
+                     if "gemm_bound_dispatches" in mc else "."))
     md.append("")
     stats = _csv_rows(a.trace, "kernel_stats.csv")
     if stats:
