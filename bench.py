@@ -679,6 +679,8 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="autotuner cache (JSON, keyed by mode and step shape)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--gradient-only", action="store_true",
+                    help="only run the gradient leg (profiling) and print its record")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -701,6 +703,9 @@ def main():
     from workload import make_workload
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.gradient_only:
+        print(json.dumps({"gradient": gradient_leg(torch, P, args)}), flush=True)
+        return
     extras = [e for e in args.extras.split(",") if e]
     modes = args.modes.split(",")
     main_mode = modes[0]

@@ -466,9 +466,12 @@ ltn_status ltn_execute_grad(ltn_plan* plan, const uint64_t* slice_ids, uint64_t 
  * on the bound stream and keep the fastest (cached in `cache_path` as JSON
  * when non-NULL). In complex64 mode on a plan bound with grad != 0, the
  * adjoint products of the gradient sweep (the forward-form GEMMs of
- * ltn_execute_grad) are tuned as well: every complex64 tile that fits each
- * product shape in either operand role against the fixed rule. (Kernel
- * choice is not part of the paper's method.) Synchronises the stream. */
+ * ltn_execute_grad) are tuned as well: every complex64 tile and, for sums
+ * of 2^10 and more, every split-K tile that fits each product shape in
+ * either operand role, against the fixed rule (cache keys g0_m_k_n_bB,
+ * values [1000 kind + cfg, swap] or [-1, 0]; a cached choice that does not
+ * fit its shape falls back to the fixed rule). (Kernel choice is not part
+ * of the paper's method.) Synchronises the stream. */
 ltn_status ltn_autotune(ltn_plan* plan, int32_t mode, const char* cache_path);
 
 /* Per-step timing of one batch (debug replay outside the graph): writes

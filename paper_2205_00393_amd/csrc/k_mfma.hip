@@ -841,7 +841,8 @@ void run(const GemmDesc& d, hipStream_t st) {
 }
 
 // Split-K tiles: waves 4 x 1 for 16 and 32 complex columns, 2 x 2 otherwise;
-// configurations 4 and 5 take the three-product form.
+// configurations 4, 5 and 7 take the three-product form; 6 and 7 fit
+// products with 64 rows (the gradient's adjoint products).
 struct SplitKCfg {
   int bm, bnc, bkc;
   const char* name;
@@ -853,6 +854,8 @@ const SplitKCfg kSplitKCfgs[] = {
     {128, 64, 16, "splitk_128x64x16"},
     {128, 64, 16, "splitk_3m_128x64x16"},
     {128, 32, 16, "splitk_3m_128x32x16"},
+    {64, 32, 16, "splitk_64x32x16"},
+    {64, 64, 16, "splitk_3m_64x64x16"},
 };
 constexpr int kNumSplitK = sizeof(kSplitKCfgs) / sizeof(kSplitKCfgs[0]);
 
@@ -928,6 +931,8 @@ void launch_cgemm_splitk(const GemmDesc& d0, hipStream_t st) {
     case 3: run_splitk<128, 64, 16, 2>(d, st); break;
     case 4: run_splitk<128, 64, 16, 2, true, 3>(d, st); break;
     case 5: run_splitk<128, 32, 16, 1, true>(d, st); break;
+    case 6: run_splitk<64, 32, 16, 2>(d, st); break;
+    case 7: run_splitk<64, 64, 16, 2, true>(d, st); break;
   }
 }
 

@@ -56,8 +56,9 @@ struct ltn_plan_impl {
   };
   std::vector<Choice> choice[3];
   // adjoint products (forward-form GEMMs of the gradient sweep) by shape
-  // (m | k << 8 | n << 16): kind 1 = a complex64 tile (cfg, swap) chosen
-  // by ltn_autotune; absent = the fixed rule of enqueue_nt
+  // (m | k << 8 | n << 16): kind 1 = a complex64 tile, kind 5 = a split-K
+  // tile (cfg, swap) chosen by ltn_autotune; absent = the fixed rule of
+  // enqueue_nt
   std::map<uint32_t, Choice> adj;
   std::vector<char> needs_grad;
   hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
@@ -136,9 +137,16 @@ Layout layout(const ltn_plan* p, int B, int grad) {
     if (skinny_fits(sp.m, sp.k, sp.n)) sk = std::max<int64_t>(sk, skinny_part_elems(sp.m, sp.k, sp.n));
   l.skinny = o;
   o = al(o + (size_t)B * (size_t)sk * 8);
-  // split-K partials (largest over the steps a split-K tile fits)
+  // split-K partials (largest over the steps a split-K tile fits and, on
+  // plans bound for gradients, over the adjoint products)
   int64_t kp = 0;
-  for (auto& sp : p->steps) kp = std::max<int64_t>(kp, splitk_part_elems(sp.m, sp.k, sp.n));
+  for (auto& sp : p->steps) {
+    kp = std::max<int64_t>(kp, splitk_part_elems(sp.m, sp.k, sp.n));
+    if (grad) {
+      kp = std::max<int64_t>(kp, splitk_part_elems(sp.m, sp.n, sp.k));
+      kp = std::max<int64_t>(kp, splitk_part_elems(sp.n, sp.m, sp.k));
+    }
+  }
   l.splitk = o;
   o = al(o + (size_t)B * (size_t)kp * 8);
   l.gdesc = o;  // gradient runs: at most one descriptor per step forward, two backward
@@ -935,6 +943,29 @@ static void nt_gemm(ltn_plan* p, const float2* X, int64_t sX, const float2* Y, i
   launch_cgemm(d, LTN_C64, p->rt->st);
 }
 
+// The same product on a split-K tile (partials in the workspace's split-K
+// buffer, which the layout sizes for the adjoint products of gradient plans).
+static void nt_splitk(ltn_plan* p, const float2* X, int64_t sX, const float2* Y, int64_t sY, float2* C,
+                      int64_t sC, int m, int k, int n, uint64_t cmask, int nb, int sw, int cfg) {
+  auto& r = *p->rt;
+  const uint64_t full = (m + n) >= 64 ? ~0ull : ((1ull << (m + n)) - 1);
+  GemmDesc d{};
+  d.A = sw ? Y : X;
+  d.B = sw ? X : Y;
+  d.C = C;
+  d.sA = sw ? sY : sX;
+  d.sB = sw ? sX : sY;
+  d.sC = sC;
+  d.m = sw ? n : m;
+  d.n = sw ? m : n;
+  d.k = k;
+  d.cmask = sw ? (~cmask & full) : cmask;
+  d.nb = nb;
+  d.cfg = cfg;
+  d.part = reinterpret_cast<float2*>(r.ws + r.lay.splitk);
+  launch_cgemm_splitk(d, r.st);
+}
+
 static void enqueue_nt(ltn_plan* p, const float2* X, int64_t sX, const float2* Y, int64_t sY,
                        float2* C, int64_t sC, int m, int k, int n, uint64_t cmask, int nb) {
   auto& r = *p->rt;
@@ -942,6 +973,10 @@ static void enqueue_nt(ltn_plan* p, const float2* X, int64_t sX, const float2* Y
   const auto tuned = r.adj.find(adj_key(m, k, n));
   if (tuned != r.adj.end() && tuned->second.kind == 1) {
     nt_gemm(p, X, sX, Y, sY, C, sC, m, k, n, cmask, nb, tuned->second.swap, tuned->second.cfg);
+    return;
+  }
+  if (tuned != r.adj.end() && tuned->second.kind == 5) {
+    nt_splitk(p, X, sX, Y, sY, C, sC, m, k, n, cmask, nb, tuned->second.swap, tuned->second.cfg);
     return;
   }
   for (int sw = 0; sw < 2; ++sw) {
@@ -1387,16 +1422,25 @@ void tune_adjoint(ltn_plan* p, std::map<std::string, std::pair<int, int>>& cache
       const auto it = cache.find(o.str());
       Choice pick;  // kind 0: the fixed rule
       if (it != cache.end()) {
-        if (it->second.first >= 1000) {
+        const int kind = it->second.first >= 1000 ? it->second.first / 1000 : 0;
+        const int cfg = it->second.first % 1000, sw = it->second.second;
+        if (kind == 1 && (sw ? gemm_config_fits(cfg, n, k, m, LTN_C64) : gemm_config_fits(cfg, m, k, n, LTN_C64))) {
           pick.kind = 1;
-          pick.cfg = it->second.first - 1000;
-          pick.swap = it->second.second;
+          pick.cfg = cfg;
+          pick.swap = sw;
+        } else if (kind == 5 && (sw ? splitk_config_fits(cfg, n, k, m) : splitk_config_fits(cfg, m, k, n))) {
+          pick.kind = 5;
+          pick.cfg = cfg;
+          pick.swap = sw;
         }
       } else {
         auto run = [&](const Choice& c) {
           if (c.kind == 1)
             nt_gemm(p, Xs, int64_t(1) << rc, Ys, int64_t(1) << other.rank, C, int64_t(1) << self.rank,
                     m, k, n, cmask, r.B, c.swap, c.cfg);
+          else if (c.kind == 5)
+            nt_splitk(p, Xs, int64_t(1) << rc, Ys, int64_t(1) << other.rank, C, int64_t(1) << self.rank,
+                      m, k, n, cmask, r.B, c.swap, c.cfg);
           else {
             r.adj.erase(key);
             enqueue_nt(p, Xs, int64_t(1) << rc, Ys, int64_t(1) << other.rank, C, int64_t(1) << self.rank,
@@ -1409,6 +1453,15 @@ void tune_adjoint(ltn_plan* p, std::map<std::string, std::pair<int, int>>& cache
             if (sw ? gemm_config_fits(c, n, k, m, LTN_C64) : gemm_config_fits(c, m, k, n, LTN_C64)) {
               Choice ch;
               ch.kind = 1;
+              ch.cfg = c;
+              ch.swap = sw;
+              cands.push_back(ch);
+            }
+        for (int sw = 0; sw < 2; ++sw)
+          for (int c = 0; c < splitk_config_count(); ++c)
+            if (sw ? splitk_config_fits(c, n, k, m) : splitk_config_fits(c, m, k, n)) {
+              Choice ch;
+              ch.kind = 5;
               ch.cfg = c;
               ch.swap = sw;
               cands.push_back(ch);
@@ -1428,7 +1481,7 @@ void tune_adjoint(ltn_plan* p, std::map<std::string, std::pair<int, int>>& cache
             pick = c;
           }
         }
-        cache[o.str()] = pick.kind == 1 ? std::make_pair(1000 + pick.cfg, pick.swap) : std::make_pair(-1, 0);
+        cache[o.str()] = pick.kind > 0 ? std::make_pair(1000 * pick.kind + pick.cfg, pick.swap) : std::make_pair(-1, 0);
         dirty = true;
       }
       r.adj[key] = pick;

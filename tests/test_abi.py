@@ -55,8 +55,8 @@ def test_permute_argument_checks_without_gpu():
 
 def test_kernel_names_without_gpu():
     """Kernel choices are named on the host: the complex64 tiles 10-15 and
-    split-K tiles 4-5 are the three-product form (c64_3m_*, splitk_3m_*),
-    tiles 0-9 and split-K 0-3 the direct form; a split kind has no name in
+    split-K tiles 4, 5 and 7 are the three-product form (c64_3m_*, splitk_3m_*),
+    tiles 0-9 and split-K 0-3 and 6 the direct form; a split kind has no name in
     complex64 mode and choices past the tables are "?"."""
     import paper_2205_00393_amd as P
     direct = [P.kernel_name(1, c) for c in range(10)]
@@ -65,9 +65,10 @@ def test_kernel_names_without_gpu():
     assert all(n.startswith("c64_3m_") for n in three)
     assert len(set(direct + three)) == 16
     assert P.kernel_name(1, 16) == "?" and P.kernel_name(1, -1) == "?"
-    assert [P.kernel_name(5, c) for c in range(6)][3:] == \
-        ["splitk_128x64x16", "splitk_3m_128x64x16", "splitk_3m_128x32x16"]
-    assert P.kernel_name(5, 6) == "?"
+    assert [P.kernel_name(5, c) for c in range(8)][3:] == \
+        ["splitk_128x64x16", "splitk_3m_128x64x16", "splitk_3m_128x32x16", "splitk_64x32x16",
+         "splitk_3m_64x64x16"]
+    assert P.kernel_name(5, 8) == "?"
     assert P.kernel_name(2, 0, "c64") == "?"
     assert P.kernel_name(2, 16, "split_bf16") == "split_dma1x4_128x128x16"
     assert P.kernel_name(3, 1) == "narrow_rows" and P.kernel_name(4, 0) == "split_sum"

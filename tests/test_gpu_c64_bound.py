@@ -2,7 +2,7 @@
 
 A two-leaf network whose only step is one complex GEMM C = A B runs in
 complex64 mode on every complex64 tile that fits (kind 1: direct tiles 0-9,
-three-product tiles 10-15; kind 5: split-K tiles 0-5 for a long sum), in both
+three-product tiles 10-15; kind 5: split-K tiles 0-7 for a long sum), in both
 operand roles, forced through ltn_set_step_kernel; the exact product of the
 complex64 inputs (complex128) is the reference. u = 2^-23 (so as not to
 assume round-to-nearest inside the matrix core), sums of L terms add at most
@@ -90,7 +90,7 @@ def test_c64_gemm_within_analytic_bound(torch, m, k, n, operands):
     exact = a.astype(np.complex128) @ b.astype(np.complex128)
     K = 1 << k
     ran = {False: 0, True: 0}
-    for kind, n_cfg in ((1, 16), (5, 6)):
+    for kind, n_cfg in ((1, 16), (5, 8)):
         for cfg in range(n_cfg):
             for swap in (0, 1):
                 try:

@@ -97,6 +97,44 @@ def test_rqc20_gradient_autotuned(torch, tmp_path):
     assert np.array_equal(g, g2)
 
 
+def _splitk64_fits(cfg, m, k, n):
+    """Split-K configuration 6 (64 x 32 tile) or 7 (64 x 64) fits rows m,
+    sum k, columns n (sums of 2^10 and more, chunks of at least 2^8 and of
+    at most 2^(23 - m - n) per slice, each chunk at least one 16-deep k-tile)."""
+    if k < 10:
+        return False
+    c = min(23 - (m + n), k - 8)
+    return c > 0 and m >= 6 and n >= (5 if cfg == 6 else 6) and k - c >= 4
+
+
+def test_rqc20_gradient_split_k_adjoint(torch, tmp_path):
+    """Adjoint products with long sums forced onto the split-K tiles for
+    64-row products (a tuning cache whose adjoint entries name split-K
+    configuration 6, direct form, or 7, three-product form): the gradient
+    still matches the oracle's adjoint gradient."""
+    import json
+    path = os.path.join(GOLDEN, "rqc20_grad_reference.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden gradient reference not generated")
+    ref = np.load(path)
+    w = make_workload("rqc20_grad")
+    cache = str(tmp_path / "tune.json")
+    _run(torch, w, tune_cache=cache)
+    keys = json.load(open(cache))
+    for cfg in (6, 7):
+        fits = [k for k in keys if k.startswith("g0_") and _splitk64_fits(cfg, *map(int, k.split("_")[1:4]))]
+        assert fits, "no adjoint product has a long sum that the 64-row split-K tile fits"
+        forced = dict(keys)
+        for k in fits:
+            forced[k] = [5000 + cfg, 0]
+        path2 = str(tmp_path / f"forced{cfg}.json")
+        json.dump(forced, open(path2, "w"))
+        banner(f"rqc20 gradient, split-K configuration {cfg} on adjoint shapes {fits}")
+        psi, loss, g = _run(torch, w, tune_cache=path2)
+        assert rel_l2(psi, ref["amplitudes"]) < 1e-4
+        assert rel_l2(g, ref["grad"]) < 1e-3
+
+
 def test_gradient_reuses_one_batch_forward(torch):
     """On a plan bound for gradients with all slices in one batch, the
     autograd forward (ltn_execute) leaves its intermediates in the gradient

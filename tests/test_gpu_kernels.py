@@ -190,7 +190,7 @@ def test_split_sum_single_step(torch, m, k, n):
         assert err < 1e-5
 
 
-@pytest.mark.parametrize("m,k,n", [(9, 12, 4), (7, 11, 6), (4, 12, 9), (10, 16, 5), (12, 10, 10)])
+@pytest.mark.parametrize("m,k,n", [(9, 12, 4), (7, 11, 6), (4, 12, 9), (10, 16, 5), (12, 10, 10), (6, 14, 6)])
 def test_splitk_single_step(torch, m, k, n):
     """The split-K complex64 MFMA GEMM (kind 5) alone on one-step networks:
     C = A B with 2^m x 2^k and 2^k x 2^n complex64 operands, every tile
@@ -210,7 +210,7 @@ def test_splitk_single_step(torch, m, k, n):
     runs = 0
     for mode in ("c64", "split_f16", "split_bf16"):
         for swap in (0, 1):
-            for cfg in range(6):
+            for cfg in range(8):
                 try:
                     plan.set_step_kernel(0, mode, 5, cfg, swap, 1)
                 except P.LtnError:
