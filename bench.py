@@ -59,6 +59,20 @@ def counter_traffic(workload, mode):
     return rec["traffic_bytes_per_launch"]
 
 
+def step_roofline(kind, tile, m, k, n, batch):
+    """Algorithmic flops, executed matrix flops, algorithmic bytes of one
+    matrix-core step (kind 1/5 complex64 tiles, kind 2 split tiles) over a
+    batch, and whether it is GEMM-bound: executed flops per algorithmic byte
+    at or above the ridge of its matrix peak and the 8 TB/s HBM peak.
+    Executed flops per complex MAC: 8 on direct complex64 tiles, 6 on the
+    three-product ones (names with _3m_), 24 on split tiles."""
+    f = 8.0 * (1 << (m + k + n)) * batch
+    fx = f * (3.0 if kind == 2 else (0.75 if "_3m_" in tile else 1.0))
+    by = 8.0 * ((1 << (m + k)) + (1 << (n + k)) + (1 << (m + n))) * batch
+    peak = PEAK_F16_MFMA_TFLOPS if kind == 2 else PEAK_FP32_MFMA_TFLOPS
+    return f, fx, by, fx / by >= peak / PEAK_HBM_GBS * 1e3
+
+
 def sig6(v):
     """Six significant digits (small errors stay visible)."""
     return float(f"{v:.6g}") if isinstance(v, float) else v
@@ -272,19 +286,15 @@ def time_plan(torch, P, pr, workload, modes, args, tag, fuse_rank=0, golden=None
             kind, _, _, _ = plan.step_kernel(k, mode)
             for name, kinds in fam.items():
                 if kind in kinds:
-                    f = 8.0 * (1 << (st["m"] + st["k"] + st["n"])) * batch
+                    tile = plan.step_kernel_name(k, mode)
+                    f, fx, by, bound = step_roofline(kind, tile, st["m"], st["k"], st["n"], batch)
                     e = kern[name]
                     e["launches"] += 1
                     e["flops_per_batch"] += f
-                    tile = plan.step_kernel_name(k, mode)
                     e["tiles"][tile] = e["tiles"].get(tile, 0) + 1
-                    fx = f * (3.0 if kind == 2 else (0.75 if "_3m_" in tile else 1.0))
-                    by = 8.0 * ((1 << (st["m"] + st["k"])) + (1 << (st["n"] + st["k"])) + (1 << (st["m"] + st["n"]))) * batch
                     e["exec_flops_per_batch"] += fx
                     e["alg_bytes_per_batch"] += by
                     if "steps" in e:
-                        pk = PEAK_F16_MFMA_TFLOPS if kind == 2 else PEAK_FP32_MFMA_TFLOPS
-                        bound = fx / by >= pk / PEAK_HBM_GBS * 1e3
                         e["steps"].append([k, st["m"], st["k"], st["n"], tile, round(float(ms[k]), 4), bound])
                         if bound:
                             g = e["gemm_bound"]
