@@ -3,11 +3,13 @@
 //   C[merge(m, n)] = sum_k A[m * K + k] * B[n * K + k]     (complex64)
 //
 // Both operands keep the contracted index innermost (the plan's layout
-// rule), so this is an "NT" GEMM. A complex product is run as a real GEMM
-// of size M x 2N x 2K: A is used as stored (re, im interleaved along k) and
-// each complex b of B becomes the real 2x2 block [[br, -bi], [bi, br]]
-// (rows: output re / im, columns: input re / im), built while B is read
-// from LDS. The real output [M][2N] is then complex C[m][n] interleaved.
+// rule), so this is an "NT" GEMM. The direct tiles run a complex product
+// as a real GEMM of size M x 2N x 2K; the three-product tiles as three
+// real GEMMs of M x N x K (see k_cgemm_c64). In the direct form A is used
+// as stored (re, im interleaved along k) and each complex b of B becomes
+// the real 2x2 block [[br, -bi], [bi, br]] (rows: output re / im, columns:
+// input re / im), built while B is read from LDS. The real output [M][2N]
+// is then complex C[m][n] interleaved.
 //
 // v_mfma_f32_32x32x2_f32 consumes, per lane l, A[l % 32][l / 32] and
 // B[l / 32][l % 32]; lane l holds C[8 g + 4 (l / 32) + q][l % 32] in
@@ -162,10 +164,10 @@ struct Cfg {
 //   P1 = Ar Br^T,  P2 = Ai Bi^T,  P3 = (Ar + Ai)(Br + Bi)^T,
 //   Re C = P1 - P2,  Im C = P3 - P1 - P2,
 // three real GEMMs of M x N x K, i.e. 3 real MACs per complex MAC instead
-// of the 4 of the 2x2 real form. The real part is formed exactly as in the
-// direct form; the imaginary part's error bound grows from terms in
-// |Ar||Bi| + |Ai||Br| to terms in (|Ar| + |Ai|)(|Br| + |Bi|), at most
-// about twice as large. Lane l's MFMA operand is row l % 32, k l / 32 of A
+// of the 4 of the 2x2 real form. The real part's error bound has the form
+// of the direct form's (two sums and a subtraction instead of one sum of
+// both); the imaginary part's grows from terms in |Ar||Bi| + |Ai||Br| to
+// terms in (|Ar| + |Ai|)(|Br| + |Bi|), at most about twice as large. Lane l's MFMA operand is row l % 32, k l / 32 of A
 // and column l % 32 of B, so one 8-byte LDS read of a complex element of
 // each gives the operands of P1 and P2, and their sums those of P3; the
 // accumulators of a lane hold whole complex outputs.
