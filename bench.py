@@ -268,13 +268,8 @@ def time_plan(torch, P, pr, workload, modes, args, tag, fuse_rank=0, golden=None
             ms += plan.profile_steps(first, mode)
         ms /= reps
         # matrix-core steps: kinds 1 and 5 run k_cgemm_c64 (complex64, the
-        # split-K form included), kind 2 runs k_cgemm_split. Executed matrix
-        # flops per complex MAC: 8 on the direct complex64 tiles, 6 on the
-        # three-product ones (c64_3m_*, splitk_3m_*), 24 on the split tiles
-        # (three fp16/bf16 products of the 2x2 real form)
-        # A matrix-core step is GEMM-bound when its executed flops per
-        # algorithmic byte reach the ridge (matrix peak / 8 TB/s HBM);
-        # steps below it (short sums, large outputs) are bound by HBM.
+        # split-K form included), kind 2 runs k_cgemm_split; executed flops
+        # and the GEMM-bound test per step come from step_roofline
         fam = {"k_cgemm_c64": (1, 5), "k_cgemm_split": (2,), "k_narrow": (3,)}
         kern = {name: {"launches": 0, "flops_per_batch": 0.0, "exec_flops_per_batch": 0.0,
                        "alg_bytes_per_batch": 0.0, "ms_per_batch": 0.0, "tiles": {}} for name in fam}
